@@ -1,0 +1,257 @@
+/*
+ * bbfg.h -- C ABI of the MI355X (gfx950) generalized BB/FG permanent library.
+ *
+ * Method: M. Morse et al., "High performance Boson Sampling simulation via
+ * data-flow engines" (arXiv:2309.07027).
+ *   - Eq. (bbfg): the Balasubramanian-Bax-Franklin-Glynn formula with column
+ *     sums over rows (Sec. 2).
+ *   - Eq. (Deltak) / Eq. (bbfgrepeated): rows repeated M_k times collapse to
+ *     one row whose sign vector is summarised by Delta_k = number of -1 signs,
+ *     weighted by C(M_k, Delta_k) (Sec. 2.2).
+ *   - Sec. 2.1 / 2.2: the addends are walked in (n-ary) reflected Gray-code
+ *     order, one row changing per step, in independent contiguous chunks whose
+ *     column sums are recomputed at the chunk start.
+ *   - Sec. 4 / Eq. (bs_p): boson-sampling probabilities are squared permanents;
+ *     the Clifford & Clifford sampler and loss by mode doubling sit on top.
+ *
+ * Conventions shared by every entry point
+ *   - Complex numbers are bbfg_c128 (two doubles, real then imaginary), the
+ *     memory layout of std::complex<double>, numpy complex128 and
+ *     torch.complex128.
+ *   - A matrix argument is ROW-MAJOR: element (i, j) of an R x C matrix is at
+ *     index i*C + j.  Rows are output modes, columns are input modes (Sec. 2).
+ *   - Pointers documented "host or device" may point to host memory or to
+ *     device memory of the current HIP device; the library finds out which
+ *     with hipPointerGetAttributes and copies what it needs.  All other
+ *     pointers are host memory.
+ *   - The caller owns every buffer passed in, including outputs.  The library
+ *     keeps no reference to them after the call returns.
+ *   - Every call is synchronous: results are in place when it returns.  The
+ *     library's device work runs on the stream set with bbfg_set_stream (the
+ *     null stream by default), so it is ordered after earlier work the caller
+ *     queued on that stream.
+ *   - Every function returns 0 (BBFG_OK) or a negative bbfg_status; on error
+ *     bbfg_last_error() describes the failure (thread-local string).  Argument
+ *     errors are detected on the host before any device work.
+ *   - Calls from several host threads are serialised per device by the
+ *     library; server handles are not re-entrant.
+ */
+#ifndef BBFG_H
+#define BBFG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BBFG_VERSION 1
+/* Largest number of columns (photons) accepted by the FP64 path. */
+#define BBFG_MAX_N 48
+/* Largest number of columns accepted by the FP32 path. */
+#define BBFG_MAX_N_FP32 24
+
+typedef enum {
+    BBFG_OK = 0,
+    BBFG_EINVAL = -1,   /* bad argument: null pointer, sum(row_mult) != n_cols, negative count ... */
+    BBFG_ERANGE = -2,   /* size beyond the supported maximum */
+    BBFG_ENOMEM = -3,   /* device or pinned host allocation failed */
+    BBFG_EDEVICE = -4,  /* HIP runtime error (no device, launch failure, ...) */
+    BBFG_EBUSY = -5,    /* server job not finished yet */
+    BBFG_ENOTFOUND = -6 /* unknown server job id */
+} bbfg_status;
+
+typedef enum { BBFG_FP64 = 0, BBFG_FP32 = 1 } bbfg_precision;
+
+typedef struct {
+    double re, im;
+} bbfg_c128;
+
+/* Per-result diagnostics. */
+typedef struct {
+    double rel_err_est;  /* estimated relative error of the result: kappa * u * (n + sqrt(Q)) */
+    double kappa;        /* (sum |addend|) / |sum of addends|: conditioning of the sum */
+    uint64_t n_addends;  /* number of distinct addends C' = prod_k (M'_k + 1) (Sec. 2.2) */
+    uint64_t n_units;    /* independent work units (one wavefront each) */
+    double kernel_ms;    /* device time of the walk kernel, from HIP events on the library stream */
+} bbfg_info;
+
+/* Thread-local description of the last error (never NULL). */
+const char *bbfg_last_error(void);
+
+/* Library version (BBFG_VERSION). */
+int bbfg_version(void);
+
+/* Initialise the library on the current HIP device (optional: every entry
+ * point initialises lazily).  Errors: BBFG_EDEVICE. */
+int bbfg_init(void);
+
+/* Stream for the calling thread's subsequent calls (a hipStream_t, NULL = the
+ * null stream).  The stream must stay valid while it is set. */
+int bbfg_set_stream(void *hip_stream);
+
+/*
+ * perm_bbfg -- generalized BB/FG permanent, Eq. (bbfgrepeated) with column
+ * multiplicities N_j = 1, in FP64.
+ *
+ *   perm(A, M) = 2^{1-n} sum_Delta prod_k (-1)^{Delta_k} C(M'_k, Delta_k)
+ *                         prod_j sum_k (M'_k - 2 Delta_k) a_kj   (+ the fixed row)
+ *
+ * i.e. the permanent of the n x n matrix obtained by repeating row k of A
+ * row_mult[k] times.  One copy of a row with the smallest multiplicity is held
+ * at sign +1 (the fixed first row of Eq. bbfg, Sec. 2.2).
+ *
+ *   A        [in]  n_rows x n_cols complex matrix, row-major, host or device.
+ *                  One row per distinct output mode.
+ *   n_rows   [in]  number of rows of A, >= 0.
+ *   row_mult [in]  n_rows int32 multiplicities M_k >= 0 (host).  Rows with
+ *                  M_k = 0 are ignored.  sum_k M_k must equal n_cols.
+ *   n_cols   [in]  n (number of photons), 0 <= n <= BBFG_MAX_N.  n = 0 gives 1.
+ *   out      [out] one bbfg_c128, host or device.
+ *   info     [out] nullable, host.
+ *
+ * Result: column sums and products in FP64, re-seeded at every work-unit and
+ * Gray-block start; per-unit partials reduced across the wavefront and across
+ * units in double-double, then scaled by 2^{1-n} exactly.
+ * Errors: BBFG_EINVAL (null A/out with n > 0, negative multiplicity, sum
+ * mismatch), BBFG_ERANGE (n_cols > BBFG_MAX_N), BBFG_ENOMEM, BBFG_EDEVICE.
+ */
+int perm_bbfg(const bbfg_c128 *A, int32_t n_rows, const int32_t *row_mult, int32_t n_cols,
+              bbfg_c128 *out, bbfg_info *info);
+
+/*
+ * perm_batch -- many generalized permanents of uneven sizes in one persistent
+ * launch (the batched evaluation of App. A.4, generalised to unequal shapes and
+ * multiplicities).
+ *
+ *   batch            number of permanents, >= 0.
+ *   A_packed         all matrices, host or device; matrix b (n_rows[b] x
+ *                    n_cols[b], row-major) starts at element A_offset[b].
+ *   A_offset         batch int64 element offsets (host).
+ *   n_rows, n_cols   batch int32 shapes (host).
+ *   row_mult_packed  int32 multiplicities (host); those of matrix b start at
+ *                    row_mult_offset[b] (batch int64 offsets, host).
+ *   precision        BBFG_FP64, or BBFG_FP32 (column sums and products in
+ *                    FP32, accumulation in FP64/double-double; every n_cols[b]
+ *                    <= BBFG_MAX_N_FP32).
+ *   out              batch bbfg_c128 results, host or device.
+ *   rel_err_est      nullable, batch doubles (host): per-result error estimate.
+ *
+ * Each result is bitwise identical to perm_bbfg on the same matrix with the
+ * same precision: the work decomposition of an item depends only on its shape.
+ * Errors: as perm_bbfg, per item.
+ */
+int perm_batch(int32_t batch, const bbfg_c128 *A_packed, const int64_t *A_offset,
+               const int32_t *n_rows, const int32_t *row_mult_packed, const int64_t *row_mult_offset,
+               const int32_t *n_cols, int32_t precision, bbfg_c128 *out, double *rel_err_est);
+
+/* Kernel-only device time (ms) of the last perm_batch walk launch on this thread. */
+double perm_batch_last_kernel_ms(void);
+
+/*
+ * bs_sample -- Clifford & Clifford boson sampling (Sec. 4), ideal or lossy.
+ *
+ *   U                 m x m interferometer unitary (row-major), host or device.
+ *   m                 number of modes, 1 <= m <= 256 (lossy: m <= 128).
+ *   input_occupation  m int32 photon counts s_i >= 0 (host); n = sum s_i <=
+ *                     BBFG_MAX_N.  A count > 1 repeats that column (U_S of
+ *                     Eq. bs_p).
+ *   n_samples         number of samples, >= 0.
+ *   loss              uniform loss 1 - eta in [0, 1); 0 = ideal.  Lossy
+ *                     sampling uses the 2m x 2m dilation
+ *                     [[sqrt(eta) U, sqrt(1-eta) I], [sqrt(1-eta) U, -sqrt(eta) I]],
+ *                     photons entering the first m modes, and reports the first
+ *                     m output modes.
+ *   seed              64-bit seed.  Sample s uses key_s = SplitMix64(seed, s);
+ *                     draws 0..n-2 shuffle the columns (Fisher-Yates), draw
+ *                     n-1+(k-1) picks the k-th output mode by inverse CDF.
+ *   out_occupation    n_samples x m int32 output occupations (host).
+ *   info              nullable: kernel_ms = total walk time, n_addends = total.
+ *
+ * Errors: BBFG_EINVAL, BBFG_ERANGE, BBFG_ENOMEM, BBFG_EDEVICE.
+ */
+int bs_sample(const bbfg_c128 *U, int32_t m, const int32_t *input_occupation, int32_t n_samples,
+              double loss, uint64_t seed, int32_t *out_occupation, bbfg_info *info);
+
+/* ---------------------------------------------------------------------------
+ * Sampling server: continuous batching of Clifford & Clifford jobs.
+ * A background host thread admits queued jobs while the device-memory budget
+ * and the active-job limit allow, keeps each admitted job's matrix and partial
+ * samples resident on the device, and in every iteration evaluates the current
+ * step's permanents of ALL active jobs in one batched launch.  A job's samples
+ * are identical to bs_sample with the same arguments.
+ * ------------------------------------------------------------------------- */
+typedef struct bbfg_server bbfg_server;
+
+/* hbm_budget_bytes: device bytes the active jobs may hold (0 = 1/4 of the
+ * device).  max_active_jobs >= 1.  Errors: BBFG_EINVAL, BBFG_EDEVICE. */
+int bs_server_create(size_t hbm_budget_bytes, int32_t max_active_jobs, bbfg_server **srv);
+
+/* Queue a job (arguments as bs_sample; U is copied before the call returns).
+ * job_id receives an id > 0.  Errors: BBFG_EINVAL, BBFG_ERANGE. */
+int bs_server_submit(bbfg_server *srv, const bbfg_c128 *U, int32_t m, const int32_t *input_occupation,
+                     int32_t n_samples, double loss, uint64_t seed, uint64_t *job_id);
+
+/* Non-blocking: BBFG_EBUSY while the job runs; on completion copies
+ * n_samples x m occupations to out_occupation (host) and the job's latency
+ * (completion - submission, seconds) to latency_s (nullable), then forgets the
+ * job.  Errors: BBFG_ENOTFOUND, BBFG_EDEVICE (the job failed). */
+int bs_server_poll(bbfg_server *srv, uint64_t job_id, int32_t *out_occupation, double *latency_s);
+
+/* Blocks until all submitted jobs are finished (polled or not). */
+int bs_server_drain(bbfg_server *srv);
+
+/* Stops the worker thread and frees the server's device memory. */
+int bs_server_destroy(bbfg_server *srv);
+
+/* Server counters (host). */
+typedef struct {
+    uint64_t jobs_submitted, jobs_done, iterations, samples_done;
+    uint64_t max_active, max_queued;
+    double busy_s; /* worker time spent in device work */
+} bbfg_server_stats;
+int bs_server_stats(bbfg_server *srv, bbfg_server_stats *out);
+
+/* ---------------------------------------------------------------------------
+ * Host-only planning diagnostics (no device needed).
+ * ------------------------------------------------------------------------- */
+
+/* Work decomposition of one permanent (Sec. 2.1/2.2): how the sum over
+ * C' addends is split into per-lane prefix digits, per-unit high digits and
+ * the Gray-walked low digits. */
+typedef struct {
+    int32_t n_cols;
+    int32_t n_rows_kept;     /* rows with M_k > 0 */
+    int32_t pivot_row;       /* user row index of the row held at +1 */
+    int32_t n_lane_digits, n_high_digits, n_low_digits;
+    uint32_t lane_product;   /* prod of lane-digit radices (<= 64 * lane_groups) */
+    uint32_t lane_groups;    /* wavefronts needed to cover the lane digits */
+    uint32_t low_count;      /* Q: length of one Gray-walked block */
+    uint32_t pad;
+    uint64_t high_count;     /* H: number of high-digit combinations */
+    uint64_t n_addends;      /* C' = lane_product * high_count * low_count */
+    uint64_t n_units;        /* work units */
+} bbfg_plan_summary;
+
+/* slots: resident wavefronts assumed for the split (0 = query the device's
+ * FP64 walk occupancy).  Errors: BBFG_EINVAL, BBFG_ERANGE. */
+int bbfg_plan_query(const int32_t *row_mult, int32_t n_rows, int32_t n_cols, int32_t slots,
+                    bbfg_plan_summary *out);
+
+/* Reflected mixed-radix Gray code over `n_digits` digits with the given radices
+ * (digit 0 fastest), as walked inside a block: for t = 1 .. len-1,
+ * changed_digit[t] is the digit that moves between positions t-1 and t and
+ * direction[t] = +1 or -1 its step; entry 0 is -1 / 0.  len = prod(radices)
+ * must be <= max_len.  Errors: BBFG_EINVAL, BBFG_ERANGE. */
+int bbfg_gray_table(const int32_t *radices, int32_t n_digits, int32_t max_len,
+                    int32_t *changed_digit, int32_t *direction);
+
+/* Resident wavefronts per compute unit of the walk kernel for n_cols columns
+ * and the number of compute units (device query).  Errors: BBFG_EDEVICE. */
+int bbfg_walk_occupancy(int32_t n_cols, int32_t precision, int32_t *waves_per_cu, int32_t *n_cu);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BBFG_H */

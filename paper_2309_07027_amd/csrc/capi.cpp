@@ -1,0 +1,268 @@
+// capi.cpp -- the C ABI of include/bbfg.h: permanents and planning diagnostics.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "runtime.hpp"
+
+using namespace bbfg;
+
+namespace {
+
+// Host-side validation of one matrix shape (before any device work).
+int validate_shape(const int32_t* mult, int32_t n_rows, int32_t n_cols, int max_n)
+{
+    if (n_rows < 0) return set_error(BBFG_EINVAL, "n_rows = %d < 0", n_rows);
+    if (n_cols < 0) return set_error(BBFG_EINVAL, "n_cols = %d < 0", n_cols);
+    if (n_cols > max_n) return set_error(BBFG_ERANGE, "n_cols = %d exceeds the maximum %d", n_cols, max_n);
+    if (n_rows > 0 && !mult) return set_error(BBFG_EINVAL, "row_mult is NULL");
+    int64_t sum = 0;
+    for (int32_t i = 0; i < n_rows; ++i) {
+        if (mult[i] < 0) return set_error(BBFG_EINVAL, "row_mult[%d] = %d < 0", i, mult[i]);
+        sum += mult[i];
+    }
+    if (sum != n_cols)
+        return set_error(BBFG_EINVAL, "sum(row_mult) = %lld differs from n_cols = %d", (long long)sum, n_cols);
+    return BBFG_OK;
+}
+
+int write_results(void* out, const double* vals, size_t count)
+{
+    if (is_device_ptr(out)) {
+        BBFG_HIP(hipMemcpyAsync(out, vals, sizeof(double) * 2 * count, hipMemcpyHostToDevice, current_stream()));
+        BBFG_HIP(hipStreamSynchronize(current_stream()));
+    } else {
+        std::memcpy(out, vals, sizeof(double) * 2 * count);
+    }
+    return BBFG_OK;
+}
+
+// Makes the `elems` complex elements at A available on the device.
+int device_view(Context& c, const bbfg_c128* A, uint64_t elems, const double** out)
+{
+    if (elems == 0) {
+        *out = nullptr;
+        return BBFG_OK;
+    }
+    if (is_device_ptr(A)) {
+        *out = reinterpret_cast<const double*>(A);
+        return BBFG_OK;
+    }
+    BBFG_TRY(c.staging.ensure(sizeof(bbfg_c128) * elems));
+    BBFG_HIP(hipMemcpyAsync(c.staging.p, A, sizeof(bbfg_c128) * elems, hipMemcpyHostToDevice, current_stream()));
+    *out = c.staging.as<double>();
+    return BBFG_OK;
+}
+
+thread_local double t_batch_kernel_ms = 0.0;
+
+}  // namespace
+
+extern "C" {
+
+const char* bbfg_last_error(void) { return last_error(); }
+
+int bbfg_version(void) { return BBFG_VERSION; }
+
+int bbfg_init(void)
+{
+    Context* c = nullptr;
+    return get_context(&c);
+}
+
+int bbfg_set_stream(void* hip_stream)
+{
+    set_current_stream(reinterpret_cast<hipStream_t>(hip_stream));
+    return BBFG_OK;
+}
+
+int perm_bbfg(const bbfg_c128* A, int32_t n_rows, const int32_t* row_mult, int32_t n_cols, bbfg_c128* out,
+              bbfg_info* info)
+{
+    if (!out) return set_error(BBFG_EINVAL, "out is NULL");
+    BBFG_TRY(validate_shape(row_mult, n_rows, n_cols, kMaxN));
+    if (n_cols > 0 && !A) return set_error(BBFG_EINVAL, "A is NULL");
+    if (info) std::memset(info, 0, sizeof *info);
+    if (n_cols == 0) {
+        const double one[2] = {1.0, 0.0};
+        if (info) {
+            info->kappa = 1.0;
+            info->n_addends = 1;
+        }
+        return write_results(out, one, 1);
+    }
+    Context* c = nullptr;
+    BBFG_TRY(get_context(&c));
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    const double* Ad = nullptr;
+    BBFG_TRY(device_view(*c, A, (uint64_t)n_rows * (uint64_t)n_cols, &Ad));
+    std::vector<PermItem> items(1);
+    items[0].src = Ad;
+    items[0].src_off = 0;
+    items[0].ld = (uint32_t)n_cols;
+    items[0].n_rows = n_rows;
+    items[0].n = n_cols;
+    items[0].mult = row_mult;
+    BBFG_TRY(get_plan(*c, row_mult, n_rows, n_cols, 0, &items[0].plan));
+    double res[2], diag[2];
+    RunResult rr;
+    BBFG_TRY(run_perms(*c, items, 0, true, res, diag, &rr));
+    if (info) {
+        info->rel_err_est = diag[0];
+        info->kappa = diag[1];
+        info->n_addends = items[0].plan->n_addends;
+        info->n_units = rr.units;
+        info->kernel_ms = rr.kernel_ms;
+    }
+    return write_results(out, res, 1);
+}
+
+int perm_batch(int32_t batch, const bbfg_c128* A_packed, const int64_t* A_offset, const int32_t* n_rows,
+               const int32_t* row_mult_packed, const int64_t* row_mult_offset, const int32_t* n_cols,
+               int32_t precision, bbfg_c128* out, double* rel_err_est)
+{
+    if (batch < 0) return set_error(BBFG_EINVAL, "batch = %d < 0", batch);
+    if (batch == 0) return BBFG_OK;
+    if (!out || !A_offset || !n_rows || !row_mult_offset || !n_cols)
+        return set_error(BBFG_EINVAL, "NULL array argument");
+    if (precision != BBFG_FP64 && precision != BBFG_FP32)
+        return set_error(BBFG_EINVAL, "precision = %d is neither BBFG_FP64 nor BBFG_FP32", precision);
+    const int f32 = precision == BBFG_FP32 ? 1 : 0;
+    const int max_n = f32 ? kMaxNF32 : kMaxN;
+    uint64_t extent = 0;
+    bool any = false;
+    for (int32_t b = 0; b < batch; ++b) {
+        if (A_offset[b] < 0 || row_mult_offset[b] < 0) return set_error(BBFG_EINVAL, "negative offset at item %d", b);
+        if (n_rows[b] > 0 && !row_mult_packed) return set_error(BBFG_EINVAL, "row_mult_packed is NULL");
+        const int rc = validate_shape(n_rows[b] > 0 ? row_mult_packed + row_mult_offset[b] : nullptr, n_rows[b],
+                                      n_cols[b], max_n);
+        if (rc != BBFG_OK) return set_error(rc, "item %d: %s", b, last_error());
+        if (n_cols[b] > 0) {
+            any = true;
+            extent = std::max<uint64_t>(extent, (uint64_t)A_offset[b] + (uint64_t)n_rows[b] * (uint64_t)n_cols[b]);
+        }
+    }
+    if (any && !A_packed) return set_error(BBFG_EINVAL, "A_packed is NULL");
+    std::vector<double> res(2 * (size_t)batch, 0.0), diag(2 * (size_t)batch, 0.0);
+    t_batch_kernel_ms = 0.0;
+    if (any) {
+        Context* c = nullptr;
+        BBFG_TRY(get_context(&c));
+        std::lock_guard<std::recursive_mutex> lk(c->mu);
+        const double* Ad = nullptr;
+        BBFG_TRY(device_view(*c, A_packed, extent, &Ad));
+        std::vector<PermItem> items;
+        std::vector<int32_t> idx;
+        items.reserve((size_t)batch);
+        for (int32_t b = 0; b < batch; ++b) {
+            if (n_cols[b] == 0) continue;
+            PermItem it;
+            it.src = Ad;
+            it.ld = (uint32_t)n_cols[b];
+            it.src_off = (uint64_t)A_offset[b];
+            it.n_rows = n_rows[b];
+            it.n = n_cols[b];
+            it.mult = row_mult_packed + row_mult_offset[b];
+            BBFG_TRY(get_plan(*c, it.mult, it.n_rows, it.n, f32, &it.plan));
+            items.push_back(std::move(it));
+            idx.push_back(b);
+        }
+        std::vector<double> r2(2 * items.size()), d2(2 * items.size());
+        RunResult rr;
+        BBFG_TRY(run_perms(*c, items, f32, false, r2.data(), d2.data(), &rr));
+        t_batch_kernel_ms = rr.kernel_ms;
+        for (size_t i = 0; i < items.size(); ++i) {
+            res[2 * (size_t)idx[i]] = r2[2 * i];
+            res[2 * (size_t)idx[i] + 1] = r2[2 * i + 1];
+            diag[2 * (size_t)idx[i]] = d2[2 * i];
+        }
+    }
+    for (int32_t b = 0; b < batch; ++b)
+        if (n_cols[b] == 0) {
+            res[2 * (size_t)b] = 1.0;
+            res[2 * (size_t)b + 1] = 0.0;
+        }
+    if (rel_err_est)
+        for (int32_t b = 0; b < batch; ++b) rel_err_est[b] = diag[2 * (size_t)b];
+    return write_results(out, res.data(), (size_t)batch);
+}
+
+double perm_batch_last_kernel_ms(void) { return t_batch_kernel_ms; }
+
+int bbfg_plan_query(const int32_t* row_mult, int32_t n_rows, int32_t n_cols, int32_t slots, bbfg_plan_summary* out)
+{
+    if (!out) return set_error(BBFG_EINVAL, "out is NULL");
+    BBFG_TRY(validate_shape(row_mult, n_rows, n_cols, kMaxN));
+    if (slots < 0) return set_error(BBFG_EINVAL, "slots < 0");
+    uint64_t S = (uint64_t)slots;
+    if (slots == 0 && n_cols > 0) {
+        Context* c = nullptr;
+        BBFG_TRY(get_context(&c));
+        std::lock_guard<std::recursive_mutex> lk(c->mu);
+        BBFG_TRY(walk_slots(*c, n_cols, 0, &S));
+    }
+    HostPlan P;
+    std::string err;
+    const int rc = build_plan(row_mult, n_rows, n_cols, S, PlanParams(), P, err);
+    if (rc != BBFG_OK) return set_error(rc, "%s", err.c_str());
+    std::memset(out, 0, sizeof *out);
+    out->n_cols = P.n;
+    out->n_rows_kept = P.r;
+    out->pivot_row = P.pivot >= 0 ? P.src_row[(size_t)P.pivot] : -1;
+    out->n_lane_digits = (int32_t)P.lane_digits.size();
+    out->n_high_digits = (int32_t)P.high_digits.size();
+    out->n_low_digits = (int32_t)P.low_digits.size();
+    out->lane_product = P.lane_product;
+    out->lane_groups = P.groups;
+    out->low_count = P.Q;
+    out->high_count = P.H;
+    out->n_addends = P.n_addends;
+    out->n_units = P.n == 0 ? 0 : P.units;
+    return BBFG_OK;
+}
+
+int bbfg_gray_table(const int32_t* radices, int32_t n_digits, int32_t max_len, int32_t* changed_digit,
+                    int32_t* direction)
+{
+    if (n_digits < 0 || n_digits > 64 || (n_digits > 0 && !radices) || !changed_digit || !direction)
+        return set_error(BBFG_EINVAL, "bad arguments");
+    uint64_t len = 1;
+    std::vector<uint32_t> R((size_t)n_digits);
+    for (int i = 0; i < n_digits; ++i) {
+        if (radices[i] < 1) return set_error(BBFG_EINVAL, "radix[%d] = %d < 1", i, radices[i]);
+        R[(size_t)i] = (uint32_t)radices[i];
+        len *= (uint64_t)radices[i];
+        if (len > (uint64_t)std::max(0, max_len)) return set_error(BBFG_ERANGE, "Gray code longer than max_len");
+    }
+    std::vector<uint32_t> cur((size_t)n_digits), prev((size_t)n_digits);
+    for (uint64_t t = 0; t < len; ++t) {
+        gray_digits(t, R.data(), n_digits, cur.data());
+        changed_digit[t] = -1;
+        direction[t] = 0;
+        if (t > 0)
+            for (int i = 0; i < n_digits; ++i)
+                if (cur[(size_t)i] != prev[(size_t)i]) {
+                    changed_digit[t] = i;
+                    direction[t] = (int)cur[(size_t)i] - (int)prev[(size_t)i];
+                }
+        prev = cur;
+    }
+    return BBFG_OK;
+}
+
+int bbfg_walk_occupancy(int32_t n_cols, int32_t precision, int32_t* waves_per_cu, int32_t* n_cu)
+{
+    const int f32 = precision == BBFG_FP32 ? 1 : 0;
+    if (n_cols < 1 || n_cols > (f32 ? kMaxNF32 : kMaxN)) return set_error(BBFG_ERANGE, "n_cols out of range");
+    Context* c = nullptr;
+    BBFG_TRY(get_context(&c));
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    uint64_t S = 0;
+    BBFG_TRY(walk_slots(*c, n_cols, f32, &S));
+    if (waves_per_cu) *waves_per_cu = (int32_t)(S / (uint64_t)c->n_cu);
+    if (n_cu) *n_cu = c->n_cu;
+    return BBFG_OK;
+}
+
+}  // extern "C"

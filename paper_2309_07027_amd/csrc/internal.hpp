@@ -1,0 +1,99 @@
+// internal.hpp -- data structures shared by the host planner and the gfx950
+// kernels of the generalized BB/FG permanent (arXiv:2309.07027, Sec. 2).
+#pragma once
+
+#include <cstdint>
+
+namespace bbfg {
+
+constexpr int kWave = 64;       // CDNA wavefront width
+constexpr int kMaxN = 48;       // largest column count of the FP64 path
+constexpr int kMaxNF32 = 24;    // largest column count of the FP32 path
+constexpr int kBinomDim = kMaxN + 1;
+
+// How the sign count Delta_k of a row is obtained inside a work unit.
+//   FIXED: the row has no free sign (the pivot with M = 1); coefficient = base.
+//   LANE : a lane-prefix digit; Delta = (lane_index / stride) % radix.
+//   HIGH : a per-segment digit;  Delta = (h / stride) % radix, h = block index.
+//   LOW  : a Gray-walked digit;  Delta = reflected decode of the position t
+//          inside the block (Sec. 2.2 reflected n-ary Gray code).
+enum RowKind : int32_t { ROW_FIXED = 0, ROW_LANE = 1, ROW_HIGH = 2, ROW_LOW = 3 };
+
+// One kept row.  Column-sum coefficient = base - 2 * Delta  (Eq. Deltak), where
+// base = M'_k + (1 if the row is the pivot).  Weight factor (-1)^Delta C(mp, Delta).
+struct RowInfo {
+    int32_t base;
+    int32_t kind;
+    uint32_t radix;   // mp + 1
+    uint32_t stride;  // product of the radices of the earlier digits of the same kind
+    int32_t mp;       // M'_k
+    int32_t pad;
+};
+
+// Gray-walk table entry for position t of a block: the +-2a row that is added
+// when stepping from t-1 to t, and the signed low-digit weight at t:
+//   s(t) = prod_{low k} (-1)^{Delta_k(t)} C(M'_k, Delta_k(t)).
+struct TabEntry {
+    uint32_t row;  // index into the 2r x n array of +-2a rows (2k: +2a_k, 2k+1: -2a_k)
+    uint32_t pad;
+    double s;
+};
+
+// Device descriptor of one permanent.
+struct PermDesc {
+    uint64_t a_off;          // element offset of the r x n kept rows (complex)
+    uint64_t a2_off;         // element offset of the 2r x n +-2a rows (complex)
+    uint64_t tab_off;        // entry offset of the Gray table (Q entries)
+    uint64_t unit_base;      // slot of this permanent's unit 0 in the partial arrays
+    uint64_t units;          // number of units  (= groups * units_per_group)
+    uint64_t units_per_group;
+    uint64_t span;           // block positions per lane group (H * Q)
+    uint32_t rowinfo_off;    // entry offset of the r RowInfo records
+    int32_t n;               // columns
+    int32_t r;               // kept rows
+    uint32_t Q;              // Gray block length
+    uint32_t lane_product;   // number of valid lane indices
+    uint32_t groups;         // lane groups
+    double scale;            // 2^{1-n}
+    double err_coeff;        // u * (n + sqrt(Q)), u the unit roundoff: error estimate = kappa * err_coeff
+};
+
+// Sizes of the partial record of one unit: a complex double-double (4 doubles)
+// plus the sum of |addend| (1 double).
+constexpr int kPartialDoubles = 5;
+
+// Gather job for one matrix: element (k, j) of the kept rows is
+//   src[src_off + srcrow[srcrow_off + k] * ld + col(j)]   (complex elements)
+// with col(j) = j when srccol_off == kIdentityCols, else srccol[srccol_off + j].
+constexpr uint32_t kIdentityCols = 0xFFFFFFFFu;
+struct PrepItem {
+    const double* src;
+    uint64_t src_off;
+    uint64_t a_off;
+    uint64_t a2_off;
+    uint32_t srcrow_off;
+    uint32_t srccol_off;
+    uint32_t ld;
+    int32_t n;
+    int32_t r;
+    int32_t f32;
+};
+
+// Kernel arguments of the walk kernels (passed by value).
+struct WalkArgs {
+    const PermDesc* descs;
+    const RowInfo* rowinfo;
+    const TabEntry* tab;
+    const double* a;     // FP64 kept rows (interleaved complex)
+    const double* a2;    // FP64 +-2a rows
+    const float* af;     // FP32 copies
+    const float* a2f;
+    const double* binom; // kBinomDim x kBinomDim
+    double* partials;    // kPartialDoubles per unit slot
+    const uint32_t* unit_item;  // batch: item of each global unit
+    uint32_t* counter;          // batch: next unit
+    uint32_t total_units;       // batch: number of units
+    uint32_t pad;
+};
+
+}  // namespace bbfg

@@ -1,0 +1,25 @@
+// kernels.hpp -- launch interface between the host runtime and walk.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "internal.hpp"
+
+namespace bbfg {
+
+const void* walk_single_fn(int n, int f32);
+const void* walk_batch_fn(int bucket, int f32);
+int batch_bucket_max(int nmax, int f32);
+
+hipError_t launch_walk_single(int n, int f32, uint32_t grid, hipStream_t s, const WalkArgs& A, uint32_t item);
+hipError_t launch_walk_batch(int bucket, int f32, uint32_t grid, hipStream_t s, const WalkArgs& A);
+hipError_t launch_reset_counter(uint32_t* counter, hipStream_t s);
+hipError_t launch_prep(uint32_t items, hipStream_t s, const PrepItem* it, const uint32_t* srcrow, const uint32_t* srccol,
+                       double* a, double* a2, float* af, float* a2f);
+hipError_t launch_finalize(uint32_t items, hipStream_t s, const PermDesc* descs, const double* partials, double* out,
+                           double* diag);
+hipError_t launch_init_binom(double* tab, hipStream_t s);
+
+}  // namespace bbfg

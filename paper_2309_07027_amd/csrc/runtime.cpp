@@ -1,0 +1,379 @@
+// runtime.cpp -- device context, buffers, plan cache and the permanent engine.
+#include "runtime.hpp"
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+
+namespace bbfg {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+namespace {
+thread_local std::string t_err = "no error";
+thread_local hipStream_t t_stream = nullptr;
+std::mutex g_ctx_mu;
+std::map<int, std::unique_ptr<Context>> g_ctx;
+}  // namespace
+
+int set_error(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    t_err = buf;
+    return code;
+}
+
+const char* last_error() { return t_err.c_str(); }
+
+hipStream_t current_stream() { return t_stream; }
+void set_current_stream(hipStream_t s) { t_stream = s; }
+
+// ---------------------------------------------------------------------------
+// buffers: grow-only, reused across calls (calls are serialised per device)
+// ---------------------------------------------------------------------------
+int DevBuf::ensure(size_t bytes)
+{
+    if (bytes <= cap) return BBFG_OK;
+    size_t want = std::max<size_t>(bytes, cap + cap / 2);
+    want = (want + 4095) / 4096 * 4096;
+    if (p) {
+        (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+    if (hipMalloc(&p, want) != hipSuccess) {
+        p = nullptr;
+        (void)hipGetLastError();
+        return set_error(BBFG_ENOMEM, "hipMalloc(%zu) failed", want);
+    }
+    cap = want;
+    return BBFG_OK;
+}
+
+void DevBuf::release()
+{
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+}
+
+int PinnedBuf::ensure(size_t bytes)
+{
+    if (bytes <= cap) return BBFG_OK;
+    size_t want = std::max<size_t>(bytes, cap + cap / 2);
+    want = (want + 4095) / 4096 * 4096;
+    if (p) {
+        (void)hipHostFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+    if (hipHostMalloc(&p, want, hipHostMallocDefault) != hipSuccess) {
+        p = nullptr;
+        (void)hipGetLastError();
+        return set_error(BBFG_ENOMEM, "hipHostMalloc(%zu) failed", want);
+    }
+    cap = want;
+    return BBFG_OK;
+}
+
+void PinnedBuf::release()
+{
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    cap = 0;
+}
+
+bool is_device_ptr(const void* p)
+{
+    if (!p) return false;
+    hipPointerAttribute_t attr;
+    std::memset(&attr, 0, sizeof attr);
+    if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+}
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+int get_context(Context** out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return set_error(BBFG_EDEVICE, "no HIP device available");
+    }
+    std::lock_guard<std::mutex> lk(g_ctx_mu);
+    auto it = g_ctx.find(dev);
+    if (it != g_ctx.end()) {
+        *out = it->second.get();
+        return BBFG_OK;
+    }
+    auto c = std::make_unique<Context>();
+    c->device = dev;
+    hipDeviceProp_t prop;
+    BBFG_HIP(hipGetDeviceProperties(&prop, dev));
+    c->n_cu = prop.multiProcessorCount;
+    BBFG_HIP(hipMalloc(&c->binom, sizeof(double) * kBinomDim * kBinomDim));
+    BBFG_HIP(launch_init_binom(c->binom, nullptr));
+    BBFG_HIP(hipDeviceSynchronize());
+    BBFG_HIP(hipEventCreate(&c->ev0));
+    BBFG_HIP(hipEventCreate(&c->ev1));
+    BBFG_TRY(c->counter.ensure(256));
+    *out = c.get();
+    g_ctx[dev] = std::move(c);
+    return BBFG_OK;
+}
+
+int walk_slots(Context& c, int n, int f32, uint64_t* slots)
+{
+    const auto key = std::make_pair(n, f32);
+    auto it = c.occ_single.find(key);
+    int waves = 0;
+    if (it == c.occ_single.end()) {
+        const void* fn = walk_single_fn(n, f32);
+        if (!fn) return set_error(BBFG_ERANGE, "no walk kernel for n=%d", n);
+        int blocks = 0;
+        BBFG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, kWave, 0));
+        waves = std::max(1, blocks);
+        c.occ_single[key] = waves;
+    } else {
+        waves = it->second;
+    }
+    *slots = (uint64_t)waves * (uint64_t)c.n_cu;
+    return BBFG_OK;
+}
+
+int batch_waves(Context& c, int bucket, int f32, int* waves)
+{
+    const auto key = std::make_pair(bucket, f32);
+    auto it = c.occ_batch.find(key);
+    if (it != c.occ_batch.end()) {
+        *waves = it->second;
+        return BBFG_OK;
+    }
+    const void* fn = walk_batch_fn(bucket, f32);
+    if (!fn) return set_error(BBFG_ERANGE, "no batch kernel for bucket %d", bucket);
+    int blocks = 0;
+    BBFG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, kWave, 0));
+    *waves = std::max(1, blocks);
+    c.occ_batch[key] = *waves;
+    return BBFG_OK;
+}
+
+int get_plan(Context& c, const int32_t* mult, int n_rows, int n_cols, int f32, std::shared_ptr<const HostPlan>* out)
+{
+    std::string key;
+    key.reserve(16 + 4 * (size_t)n_rows);
+    key.append(reinterpret_cast<const char*>(&n_cols), sizeof n_cols);
+    key.push_back((char)f32);
+    key.append(reinterpret_cast<const char*>(mult), sizeof(int32_t) * (size_t)n_rows);
+    auto it = c.plans.find(key);
+    if (it != c.plans.end()) {
+        *out = it->second;
+        return BBFG_OK;
+    }
+    uint64_t slots = 1;
+    if (n_cols >= 1) BBFG_TRY(walk_slots(c, n_cols, f32, &slots));
+    auto p = std::make_shared<HostPlan>();
+    std::string err;
+    const int rc = build_plan(mult, n_rows, n_cols, slots, c.params, *p, err);
+    if (rc != BBFG_OK) return set_error(rc, "%s", err.c_str());
+    if (c.plans.size() > 8192) c.plans.clear();
+    c.plans.emplace(key, p);
+    *out = p;
+    return BBFG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// the permanent engine
+// ---------------------------------------------------------------------------
+int run_perms(Context& c, std::vector<PermItem>& items, int f32, bool single, double* out_host, double* diag_host,
+              RunResult* rr, bool sync)
+{
+    const size_t nitem = items.size();
+    if (nitem == 0) return BBFG_OK;
+    if (single && nitem != 1) return set_error(BBFG_EINVAL, "internal: single launch with %zu items", nitem);
+    hipStream_t s = current_stream();
+
+    // distinct plans (tables and row records are shared between equal shapes)
+    std::unordered_map<const HostPlan*, std::pair<size_t, size_t>> plan_slot;  // -> (rowinfo off, tab off)
+    std::vector<const HostPlan*> uniq;
+    size_t n_rowinfo = 0, n_tab = 0, n_srcrow = 0, n_srccol = 0;
+    uint64_t a_elems = 0;
+    int nmax = 0;
+    for (auto& it : items) {
+        const HostPlan* p = it.plan.get();
+        if (plan_slot.find(p) == plan_slot.end()) {
+            plan_slot[p] = {n_rowinfo, n_tab};
+            n_rowinfo += (size_t)p->r;
+            n_tab += p->table.size();
+            uniq.push_back(p);
+        }
+        n_srcrow += (size_t)p->r;
+        if (it.col_map) n_srccol += (size_t)p->n;
+        a_elems += (uint64_t)p->r * (uint64_t)p->n * 3u;  // a (r x n) + a2 (2r x n)
+        nmax = std::max(nmax, p->n);
+    }
+
+    // unit numbering: longest units first (items ordered by per-unit cost)
+    std::vector<size_t> order(nitem);
+    std::iota(order.begin(), order.end(), 0);
+    if (!single) {
+        auto cost = [&](size_t i) {
+            const HostPlan& p = *items[i].plan;
+            return (double)p.span / (double)p.units_per_group * (6.0 * p.n - 2.0);
+        };
+        std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return cost(x) > cost(y); });
+    }
+    std::vector<uint64_t> unit_base(nitem);
+    uint64_t total_units = 0;
+    for (size_t oi = 0; oi < nitem; ++oi) {
+        unit_base[order[oi]] = total_units;
+        total_units += items[order[oi]].plan->units;
+    }
+    if (total_units > 0xFFFFFFF0ull) return set_error(BBFG_ERANGE, "too many work units (%llu)", (unsigned long long)total_units);
+
+    // host metadata image
+    Layout L;
+    const size_t off_desc = L.add(sizeof(PermDesc) * nitem);
+    const size_t off_row = L.add(sizeof(RowInfo) * std::max<size_t>(1, n_rowinfo));
+    const size_t off_tab = L.add(sizeof(TabEntry) * std::max<size_t>(1, n_tab));
+    const size_t off_prep = L.add(sizeof(PrepItem) * nitem);
+    const size_t off_src = L.add(sizeof(uint32_t) * std::max<size_t>(1, n_srcrow));
+    const size_t off_col = L.add(sizeof(uint32_t) * std::max<size_t>(1, n_srccol));
+    const size_t off_uitem = single ? 0 : L.add(sizeof(uint32_t) * (size_t)total_units);
+    BBFG_TRY(c.hmeta.ensure(L.size));
+    BBFG_TRY(c.meta.ensure(L.size));
+    char* H = c.hmeta.as<char>();
+    PermDesc* hd = reinterpret_cast<PermDesc*>(H + off_desc);
+    RowInfo* hr = reinterpret_cast<RowInfo*>(H + off_row);
+    TabEntry* ht = reinterpret_cast<TabEntry*>(H + off_tab);
+    PrepItem* hp = reinterpret_cast<PrepItem*>(H + off_prep);
+    uint32_t* hs = reinterpret_cast<uint32_t*>(H + off_src);
+    uint32_t* hc = reinterpret_cast<uint32_t*>(H + off_col);
+    for (const HostPlan* p : uniq) {
+        const auto sl = plan_slot[p];
+        std::memcpy(hr + sl.first, p->rows.data(), sizeof(RowInfo) * (size_t)p->r);
+        std::memcpy(ht + sl.second, p->table.data(), sizeof(TabEntry) * p->table.size());
+    }
+    uint64_t a_cursor = 0;
+    size_t s_cursor = 0, c_cursor = 0;
+    for (size_t i = 0; i < nitem; ++i) {
+        const HostPlan& p = *items[i].plan;
+        const auto sl = plan_slot[&p];
+        PermDesc& d = hd[i];
+        std::memset(&d, 0, sizeof d);
+        d.a_off = a_cursor;
+        d.a2_off = a_cursor + (uint64_t)p.r * p.n;
+        a_cursor += (uint64_t)p.r * p.n * 3u;
+        d.tab_off = sl.second;
+        d.unit_base = unit_base[i];
+        d.units = p.units;
+        d.units_per_group = p.units_per_group;
+        d.span = p.span;
+        d.rowinfo_off = (uint32_t)sl.first;
+        d.n = p.n;
+        d.r = p.r;
+        d.Q = p.Q;
+        d.lane_product = p.lane_product;
+        d.groups = p.groups;
+        d.scale = std::ldexp(1.0, 1 - p.n);
+        d.err_coeff = p.err_coeff * (f32 ? 0x1.0p-24 : 0x1.0p-53);
+        PrepItem& q = hp[i];
+        std::memset(&q, 0, sizeof q);
+        q.src = items[i].src;
+        q.src_off = items[i].src_off;
+        q.ld = items[i].ld;
+        q.a_off = d.a_off;
+        q.a2_off = d.a2_off;
+        q.srcrow_off = (uint32_t)s_cursor;
+        q.n = p.n;
+        q.r = p.r;
+        q.f32 = f32;
+        for (int k = 0; k < p.r; ++k) {
+            const int ur = p.src_row[(size_t)k];
+            hs[s_cursor++] = (uint32_t)(items[i].row_map ? items[i].row_map[ur] : ur);
+        }
+        if (items[i].col_map) {
+            q.srccol_off = (uint32_t)c_cursor;
+            for (int j = 0; j < p.n; ++j) hc[c_cursor++] = (uint32_t)items[i].col_map[j];
+        } else {
+            q.srccol_off = kIdentityCols;
+        }
+        if (!single) {
+            uint32_t* hu = reinterpret_cast<uint32_t*>(H + off_uitem);
+            for (uint64_t u = 0; u < p.units; ++u) hu[unit_base[i] + u] = (uint32_t)i;
+        }
+    }
+
+    // device buffers
+    if (f32) BBFG_TRY(c.arena_f.ensure(sizeof(float) * 2 * std::max<uint64_t>(1, a_elems)));
+    else BBFG_TRY(c.arena_d.ensure(sizeof(double) * 2 * std::max<uint64_t>(1, a_elems)));
+    BBFG_TRY(c.partials.ensure(sizeof(double) * kPartialDoubles * (size_t)total_units));
+    BBFG_TRY(c.results.ensure(sizeof(double) * 4 * nitem));
+    BBFG_TRY(c.hres.ensure(sizeof(double) * 4 * nitem));
+    char* D = c.meta.as<char>();
+    BBFG_HIP(hipMemcpyAsync(D, H, L.size, hipMemcpyHostToDevice, s));
+
+    WalkArgs W;
+    std::memset(&W, 0, sizeof W);
+    W.descs = reinterpret_cast<const PermDesc*>(D + off_desc);
+    W.rowinfo = reinterpret_cast<const RowInfo*>(D + off_row);
+    W.tab = reinterpret_cast<const TabEntry*>(D + off_tab);
+    W.a = c.arena_d.as<double>();
+    W.a2 = c.arena_d.as<double>();
+    W.af = c.arena_f.as<float>();
+    W.a2f = c.arena_f.as<float>();
+    W.binom = c.binom;
+    W.partials = c.partials.as<double>();
+    W.unit_item = single ? nullptr : reinterpret_cast<const uint32_t*>(D + off_uitem);
+    W.counter = c.counter.as<uint32_t>();
+    W.total_units = (uint32_t)total_units;
+
+    BBFG_HIP(launch_prep((uint32_t)nitem, s, reinterpret_cast<const PrepItem*>(D + off_prep),
+                         reinterpret_cast<const uint32_t*>(D + off_src), reinterpret_cast<const uint32_t*>(D + off_col),
+                         c.arena_d.as<double>(),
+                         c.arena_d.as<double>(), c.arena_f.as<float>(), c.arena_f.as<float>()));
+    if (single) {
+        BBFG_HIP(hipEventRecord(c.ev0, s));
+        BBFG_HIP(launch_walk_single(items[0].plan->n, f32, (uint32_t)total_units, s, W, 0u));
+        BBFG_HIP(hipEventRecord(c.ev1, s));
+    } else {
+        const int bucket = batch_bucket_max(nmax, f32);
+        if (bucket < 0) return set_error(BBFG_ERANGE, "no batch kernel for n=%d", nmax);
+        int waves = 1;
+        BBFG_TRY(batch_waves(c, bucket, f32, &waves));
+        const uint64_t grid = std::min<uint64_t>((uint64_t)waves * (uint64_t)c.n_cu, total_units);
+        BBFG_HIP(launch_reset_counter(W.counter, s));
+        BBFG_HIP(hipEventRecord(c.ev0, s));
+        BBFG_HIP(launch_walk_batch(bucket, f32, (uint32_t)grid, s, W));
+        BBFG_HIP(hipEventRecord(c.ev1, s));
+    }
+    double* R = c.results.as<double>();
+    BBFG_HIP(launch_finalize((uint32_t)nitem, s, W.descs, W.partials, R, R + 2 * nitem));
+    if (rr) rr->units = total_units;
+    if (!sync) return BBFG_OK;
+    double* HR = c.hres.as<double>();
+    BBFG_HIP(hipMemcpyAsync(HR, R, sizeof(double) * 4 * nitem, hipMemcpyDeviceToHost, s));
+    BBFG_HIP(hipStreamSynchronize(s));
+    if (out_host) std::memcpy(out_host, HR, sizeof(double) * 2 * nitem);
+    if (diag_host) std::memcpy(diag_host, HR + 2 * nitem, sizeof(double) * 2 * nitem);
+    if (rr) {
+        float ms = 0.f;
+        BBFG_HIP(hipEventElapsedTime(&ms, c.ev0, c.ev1));
+        rr->kernel_ms = ms;
+        rr->units = total_units;
+    }
+    return BBFG_OK;
+}
+
+}  // namespace bbfg

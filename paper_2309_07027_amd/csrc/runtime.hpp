@@ -1,0 +1,125 @@
+// runtime.hpp -- device context, memory, errors and the permanent engine.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/bbfg.h"
+#include "internal.hpp"
+#include "kernels.hpp"
+#include "plan.hpp"
+
+namespace bbfg {
+
+// ---- errors (thread-local message) ----------------------------------------
+int set_error(int code, const char* fmt, ...);
+const char* last_error();
+
+#define BBFG_HIP(expr)                                                                              \
+    do {                                                                                            \
+        hipError_t e_ = (expr);                                                                     \
+        if (e_ != hipSuccess) return ::bbfg::set_error(BBFG_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+#define BBFG_TRY(expr)            \
+    do {                          \
+        int s_ = (expr);          \
+        if (s_ != BBFG_OK) return s_; \
+    } while (0)
+
+// ---- growable buffers -------------------------------------------------------
+struct DevBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+    int ensure(size_t bytes);
+    void release();
+    template <typename T>
+    T* as() const { return static_cast<T*>(p); }
+};
+
+struct PinnedBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+    int ensure(size_t bytes);
+    void release();
+    template <typename T>
+    T* as() const { return static_cast<T*>(p); }
+};
+
+// Byte layout helper for one upload of several arrays.
+struct Layout {
+    size_t size = 0;
+    size_t add(size_t bytes, size_t align = 256)
+    {
+        size = (size + align - 1) / align * align;
+        const size_t off = size;
+        size += bytes;
+        return off;
+    }
+};
+
+// ---- per-device context -------------------------------------------------------
+struct Context {
+    int device = -1;
+    int n_cu = 0;
+    std::recursive_mutex mu;
+    double* binom = nullptr;
+    DevBuf arena_d, arena_f, meta, partials, results, staging, counter, cc_meta;
+    PinnedBuf hmeta, hres, cc_hmeta;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    std::map<std::pair<int, int>, int> occ_single;  // (n, f32) -> waves per CU
+    std::map<std::pair<int, int>, int> occ_batch;   // (bucket, f32) -> waves per CU
+    std::unordered_map<std::string, std::shared_ptr<const HostPlan>> plans;
+    PlanParams params;
+};
+
+// Context of the current HIP device (created on first use).
+int get_context(Context** out);
+hipStream_t current_stream();
+void set_current_stream(hipStream_t s);
+
+int walk_slots(Context& c, int n, int f32, uint64_t* slots);
+int batch_waves(Context& c, int bucket, int f32, int* waves);
+int get_plan(Context& c, const int32_t* mult, int n_rows, int n_cols, int f32, std::shared_ptr<const HostPlan>* out);
+
+// Is p device memory (of any device)?
+bool is_device_ptr(const void* p);
+
+// ---- permanent engine ----------------------------------------------------------
+// One permanent to evaluate.  Its matrix is n_rows x n: row i, column j is the
+// complex element src[src_off + row(i) * ld + col(j)] of device memory, with
+// row(i) = row_map[i] (or i) and col(j) = col_map[j] (or j).
+struct PermItem {
+    const double* src = nullptr;
+    uint64_t src_off = 0;
+    uint32_t ld = 0;
+    int n_rows = 0;
+    int n = 0;
+    const int32_t* mult = nullptr;
+    const int32_t* row_map = nullptr;
+    const int32_t* col_map = nullptr;
+    std::shared_ptr<const HostPlan> plan;
+};
+
+struct RunResult {
+    double kernel_ms = 0.0;
+    uint64_t units = 0;
+};
+
+// Evaluates items (all n >= 1).  The (re, im) results stay in c.results (item
+// order) and, when out_host is not null, are copied to out_host[2*i]; the
+// diagnostics (err_est, kappa) to diag_host[2*i].  With sync = false nothing is
+// copied back and the stream is not synchronised (the caller queues more work
+// that reads c.results).  single = true uses the one-permanent launch.
+int run_perms(Context& c, std::vector<PermItem>& items, int f32, bool single, double* out_host, double* diag_host,
+              RunResult* rr, bool sync = true);
+
+}  // namespace bbfg

@@ -1,0 +1,265 @@
+// sampler.cpp -- Clifford & Clifford boson sampling (arXiv:2309.07027, Sec. 4)
+// on top of the batched generalized BB/FG permanent.
+//
+// One sample (ideal, or lossy via the 2m x 2m dilation of Sec. 4):
+//   1. the n input columns (mode i taken s_i times, Eq. bs_p) are put in a
+//      uniformly random order pi (Fisher-Yates);
+//   2. for k = 1..n the output mode r_k is drawn with probability proportional
+//      to |perm A[(r_1..r_{k-1}, r), (pi_1..pi_k)]|^2; by Laplace expansion
+//      along row r this needs only the k permanents of the prefix rows
+//      (repeated rows -> multiplicities, Eq. bbfgrepeated) with one of the k
+//      columns removed;
+//   3. the sample is the occupation of the first m output modes.
+// Random numbers (SplitMix64) for sample s of a job with seed `seed`:
+//   key_s = draw(seed, s); draws 0..n-2 run Fisher-Yates for i = n-1 .. 1
+//   (draw n-1-i, j = ((x >> 32) * (i + 1)) >> 32); draw n-1+(k-1) gives the
+//   uniform u = (x >> 11) * 2^-53 of step k.
+#include "sampler.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <map>
+
+#include "cc_kernels.hpp"
+
+namespace bbfg {
+
+uint64_t splitmix64_draw(uint64_t key, uint64_t c)
+{
+    uint64_t z = key + (c + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+int cc_validate(const void* U, int m, const int32_t* occ, int n_samples, double loss)
+{
+    if (!U) return set_error(BBFG_EINVAL, "U is NULL");
+    if (!occ) return set_error(BBFG_EINVAL, "input_occupation is NULL");
+    if (!(loss >= 0.0 && loss < 1.0)) return set_error(BBFG_EINVAL, "loss = %g is outside [0, 1)", loss);
+    if (m < 1) return set_error(BBFG_EINVAL, "m = %d < 1", m);
+    if (m > (loss > 0.0 ? 128 : 256)) return set_error(BBFG_ERANGE, "m = %d exceeds the maximum", m);
+    if (n_samples < 0) return set_error(BBFG_EINVAL, "n_samples < 0");
+    int64_t n = 0;
+    for (int i = 0; i < m; ++i) {
+        if (occ[i] < 0) return set_error(BBFG_EINVAL, "input_occupation[%d] < 0", i);
+        n += occ[i];
+    }
+    if (n > kMaxN) return set_error(BBFG_ERANGE, "%lld photons exceed BBFG_MAX_N", (long long)n);
+    return BBFG_OK;
+}
+
+size_t cc_job_footprint(int m, int n, int n_samples, double loss)
+{
+    const size_t rows = loss > 0.0 ? 2 * (size_t)m : (size_t)m;
+    const size_t nn = (size_t)n;
+    // job matrix + U copy + the share of the step working set at k = n
+    return 16 * rows * nn + 16 * (size_t)m * (size_t)m + (size_t)n_samples * (48 * nn * nn * nn + 4096);
+}
+
+int cc_job_init(Context& c, CCJob& job, const double* U, bool U_on_device, int m, const int32_t* occ, int n_samples,
+                double loss, uint64_t seed)
+{
+    hipStream_t s = current_stream();
+    job.m = m;
+    job.loss = loss;
+    job.rows = loss > 0.0 ? 2 * m : m;
+    job.seed = seed;
+    job.n_samples = n_samples;
+    job.cols.clear();
+    for (int i = 0; i < m; ++i)
+        for (int t = 0; t < occ[i]; ++t) job.cols.push_back(i);
+    job.n = (int)job.cols.size();
+    job.samples.assign((size_t)n_samples, CCSample());
+    job.out.assign((size_t)n_samples * (size_t)m, 0);
+    job.started = job.finished = 0;
+    if (job.n == 0) return BBFG_OK;
+    // device: [U (m x m) | cols (n int32)] staging, then A
+    const size_t ubytes = 16 * (size_t)m * (size_t)m;
+    BBFG_TRY(c.staging.ensure(ubytes + 4 * (size_t)job.n + 256));
+    char* st = c.staging.as<char>();
+    const double* Ud = U;
+    if (!U_on_device) {
+        BBFG_HIP(hipMemcpyAsync(st, U, ubytes, hipMemcpyHostToDevice, s));
+        Ud = reinterpret_cast<const double*>(st);
+    }
+    int32_t* cols_d = reinterpret_cast<int32_t*>(st + (ubytes + 255) / 256 * 256);
+    BBFG_HIP(hipMemcpyAsync(cols_d, job.cols.data(), 4 * (size_t)job.n, hipMemcpyHostToDevice, s));
+    BBFG_TRY(job.A.ensure(16 * (size_t)job.rows * (size_t)job.n));
+    const double eta = 1.0 - loss;
+    BBFG_HIP(launch_build_job_matrix(Ud, m, cols_d, job.n, std::sqrt(eta), std::sqrt(1.0 - eta), loss > 0.0 ? 1 : 0,
+                                     job.A.as<double>(), s));
+    BBFG_HIP(hipStreamSynchronize(s));  // the staging buffer is reused by later calls
+    return BBFG_OK;
+}
+
+void cc_start_sample(CCJob& job, int s)
+{
+    CCSample& S = job.samples[(size_t)s];
+    S.key = splitmix64_draw(job.seed, (uint64_t)s);
+    S.k = 1;
+    S.prefix.clear();
+    S.pi.resize((size_t)job.n);
+    for (int b = 0; b < job.n; ++b) S.pi[(size_t)b] = b;
+    for (int i = job.n - 1; i >= 1; --i) {
+        const uint64_t x = splitmix64_draw(S.key, (uint64_t)(job.n - 1 - i));
+        const int j = (int)(((x >> 32) * (uint64_t)(i + 1)) >> 32);
+        std::swap(S.pi[(size_t)i], S.pi[(size_t)j]);
+    }
+}
+
+namespace {
+
+void finish_sample(CCJob& job, int s)
+{
+    const CCSample& S = job.samples[(size_t)s];
+    int32_t* o = job.out.data() + (size_t)s * (size_t)job.m;
+    for (int i = 0; i < job.m; ++i) o[i] = 0;
+    for (int32_t r : S.prefix)
+        if (r < job.m) o[r]++;
+    job.finished++;
+}
+
+}  // namespace
+
+int cc_step(Context& c, std::vector<ActiveSample>& act, double* kernel_ms, uint64_t* addends)
+{
+    hipStream_t s = current_stream();
+    std::vector<PermItem> items;
+    std::deque<std::vector<int32_t>> keep;  // multiplicities, row and column maps (stable addresses)
+    std::vector<CCStep> steps;
+    std::vector<int32_t> pis;
+    std::vector<size_t> act_of_step;
+    for (size_t ai = 0; ai < act.size(); ++ai) {
+        CCJob& J = *act[ai].job;
+        CCSample& S = J.samples[(size_t)act[ai].s];
+        if (J.n == 0 || S.k > J.n) continue;
+        const int k = S.k;
+        CCStep st;
+        std::memset(&st, 0, sizeof st);
+        st.A = J.A.as<double>();
+        st.rows = J.rows;
+        st.n = J.n;
+        st.k = k;
+        st.pi_off = (uint32_t)pis.size();
+        for (int l = 0; l < k; ++l) pis.push_back(S.pi[(size_t)l]);
+        const uint64_t x = splitmix64_draw(S.key, (uint64_t)(J.n - 1 + (k - 1)));
+        st.u = (double)(x >> 11) * 0x1.0p-53;
+        if (k >= 2) {
+            std::map<int32_t, int32_t> cnt;
+            for (int32_t r : S.prefix) cnt[r]++;
+            keep.emplace_back();
+            std::vector<int32_t>& rowmap = keep.back();
+            keep.emplace_back();
+            std::vector<int32_t>& mult = keep.back();
+            for (auto& kv : cnt) {
+                rowmap.push_back(kv.first);
+                mult.push_back(kv.second);
+            }
+            std::shared_ptr<const HostPlan> plan;
+            BBFG_TRY(get_plan(c, mult.data(), (int)mult.size(), k - 1, 0, &plan));
+            st.minor_off = (uint32_t)items.size();
+            for (int l = 0; l < k; ++l) {
+                keep.emplace_back();
+                std::vector<int32_t>& colmap = keep.back();
+                for (int b = 0; b < k; ++b)
+                    if (b != l) colmap.push_back(S.pi[(size_t)b]);
+                PermItem it;
+                it.src = J.A.as<double>();
+                it.src_off = 0;
+                it.ld = (uint32_t)J.n;
+                it.n_rows = (int)mult.size();
+                it.n = k - 1;
+                it.mult = mult.data();
+                it.row_map = rowmap.data();
+                it.col_map = colmap.data();
+                it.plan = plan;
+                if (addends) *addends += plan->n_addends;
+                items.push_back(std::move(it));
+            }
+        }
+        steps.push_back(st);
+        act_of_step.push_back(ai);
+    }
+    if (steps.empty()) return BBFG_OK;
+    RunResult rr;
+    if (!items.empty()) BBFG_TRY(run_perms(c, items, 0, false, nullptr, nullptr, &rr, false));
+
+    Layout L;
+    const size_t o_steps = L.add(sizeof(CCStep) * steps.size());
+    const size_t o_pi = L.add(sizeof(int32_t) * pis.size());
+    const size_t o_drawn = L.add(sizeof(int32_t) * steps.size());
+    const size_t o_wsum = L.add(sizeof(double) * steps.size());
+    BBFG_TRY(c.cc_hmeta.ensure(L.size));
+    BBFG_TRY(c.cc_meta.ensure(L.size));
+    char* H = c.cc_hmeta.as<char>();
+    char* D = c.cc_meta.as<char>();
+    std::memcpy(H + o_steps, steps.data(), sizeof(CCStep) * steps.size());
+    std::memcpy(H + o_pi, pis.data(), sizeof(int32_t) * pis.size());
+    BBFG_HIP(hipMemcpyAsync(D, H, o_drawn, hipMemcpyHostToDevice, s));
+    BBFG_HIP(launch_cc_weights((uint32_t)steps.size(), reinterpret_cast<const CCStep*>(D + o_steps),
+                               reinterpret_cast<const int32_t*>(D + o_pi), c.results.as<double>(),
+                               reinterpret_cast<int32_t*>(D + o_drawn), reinterpret_cast<double*>(D + o_wsum), s));
+    BBFG_HIP(hipMemcpyAsync(H + o_drawn, D + o_drawn, L.size - o_drawn, hipMemcpyDeviceToHost, s));
+    BBFG_HIP(hipStreamSynchronize(s));
+    if (!items.empty() && kernel_ms) {
+        float ms = 0.f;
+        BBFG_HIP(hipEventElapsedTime(&ms, c.ev0, c.ev1));
+        *kernel_ms += ms;
+    }
+    const int32_t* drawn = reinterpret_cast<const int32_t*>(H + o_drawn);
+    for (size_t i = 0; i < steps.size(); ++i) {
+        ActiveSample& a = act[act_of_step[i]];
+        CCSample& S = a.job->samples[(size_t)a.s];
+        S.prefix.push_back(drawn[i]);
+        S.k++;
+        if (S.k > a.job->n) finish_sample(*a.job, a.s);
+    }
+    return BBFG_OK;
+}
+
+}  // namespace bbfg
+
+using namespace bbfg;
+
+extern "C" int bs_sample(const bbfg_c128* U, int32_t m, const int32_t* input_occupation, int32_t n_samples,
+                         double loss, uint64_t seed, int32_t* out_occupation, bbfg_info* info)
+{
+    BBFG_TRY(cc_validate(U, m, input_occupation, n_samples, loss));
+    if (n_samples > 0 && !out_occupation) return set_error(BBFG_EINVAL, "out_occupation is NULL");
+    if (info) std::memset(info, 0, sizeof *info);
+    if (n_samples == 0) return BBFG_OK;
+    int64_t n = 0;
+    for (int i = 0; i < m; ++i) n += input_occupation[i];
+    if (n == 0) {
+        std::memset(out_occupation, 0, sizeof(int32_t) * (size_t)n_samples * (size_t)m);
+        return BBFG_OK;
+    }
+    Context* c = nullptr;
+    BBFG_TRY(get_context(&c));
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    CCJob job;
+    BBFG_TRY(cc_job_init(*c, job, reinterpret_cast<const double*>(U), is_device_ptr(U), m, input_occupation, n_samples,
+                         loss, seed));
+    // samples advance in lock-step, in waves of at most kWaveSamples
+    constexpr int kWaveSamples = 1024;
+    double kms = 0.0;
+    uint64_t adds = 0;
+    for (int s0 = 0; s0 < n_samples; s0 += kWaveSamples) {
+        const int s1 = std::min(n_samples, s0 + kWaveSamples);
+        std::vector<ActiveSample> act;
+        for (int s = s0; s < s1; ++s) {
+            cc_start_sample(job, s);
+            act.push_back({&job, s});
+        }
+        for (int k = 1; k <= job.n; ++k) BBFG_TRY(cc_step(*c, act, &kms, &adds));
+    }
+    std::memcpy(out_occupation, job.out.data(), sizeof(int32_t) * job.out.size());
+    if (info) {
+        info->kernel_ms = kms;
+        info->n_addends = adds;
+    }
+    return BBFG_OK;
+}

@@ -1,0 +1,273 @@
+// server.cpp -- continuous-batching boson-sampling server.
+//
+// The paper scales Clifford & Clifford sampling by running one sampler per
+// accelerator and gathering the samples (Sec. 4).  On one GPU the analogue is
+// to keep many sampling jobs in flight and to evaluate the current step of all
+// of them together: a worker thread admits queued jobs while the device-memory
+// budget and the active-job limit allow, keeps every admitted job's matrix and
+// sample state resident, and in each iteration advances every unfinished
+// sample of every active job by one step with ONE batched permanent launch
+// (all minors, uneven sizes) and ONE weights-and-draw launch.  Jobs admitted
+// later simply join the next iteration.  A job's samples depend only on its
+// own arguments (the per-item work split and the reduction orders are fixed by
+// the item's shape), so they are bitwise identical to bs_sample's.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "sampler.hpp"
+
+using namespace bbfg;
+using Clock = std::chrono::steady_clock;
+
+namespace {
+
+struct SJob {
+    uint64_t id = 0;
+    std::vector<double> U;  // host copy, m x m complex
+    int m = 0;
+    std::vector<int32_t> occ;
+    int n_samples = 0;
+    double loss = 0.0;
+    uint64_t seed = 0;
+    size_t footprint = 0;
+    Clock::time_point t_submit, t_done;
+    int state = 0;  // 0 queued, 1 active, 2 done, 3 failed
+    int err_code = 0;
+    std::string err;
+    std::unique_ptr<CCJob> cc;
+    std::vector<int32_t> out;
+};
+
+}  // namespace
+
+struct bbfg_server {
+    Context* ctx = nullptr;
+    int device = 0;
+    size_t budget = 0;
+    int max_active = 1;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::thread worker;
+    bool stop = false;
+    uint64_t next_id = 1;
+    std::deque<std::shared_ptr<SJob>> queue;
+    std::vector<std::shared_ptr<SJob>> active;  // worker thread only
+    std::unordered_map<uint64_t, std::shared_ptr<SJob>> jobs;
+    size_t used = 0;
+    size_t outstanding = 0;  // queued + active
+    bbfg_server_stats st{};
+    hipStream_t stream = nullptr;
+
+    void run();
+    void fail_active(int code, const std::string& msg);
+};
+
+void bbfg_server::fail_active(int code, const std::string& msg)
+{
+    std::lock_guard<std::mutex> lk(mu);
+    for (auto& j : active) {
+        j->state = 3;
+        j->err_code = code;
+        j->err = msg;
+        j->t_done = Clock::now();
+        j->cc.reset();
+        used -= j->footprint;
+        --outstanding;
+    }
+    active.clear();
+    cv_done.notify_all();
+}
+
+void bbfg_server::run()
+{
+    (void)hipSetDevice(device);
+    set_current_stream(stream);
+    for (;;) {
+        std::vector<std::shared_ptr<SJob>> admitted;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            for (;;) {
+                while (!stop && !queue.empty() && (int)(active.size() + admitted.size()) < max_active) {
+                    auto& j = queue.front();
+                    const bool empty = active.empty() && admitted.empty();
+                    if (!empty && used + j->footprint > budget) break;  // wait for memory to free up
+                    used += j->footprint;
+                    j->state = 1;
+                    admitted.push_back(j);
+                    queue.pop_front();
+                }
+                if (!active.empty() || !admitted.empty() || stop) break;  // (stop: queued jobs never start)
+                cv_work.wait(lk);
+            }
+            if (stop && active.empty() && admitted.empty()) return;
+            const uint64_t na = active.size() + admitted.size();
+            if (na > st.max_active) st.max_active = na;
+        }
+        const auto t0 = Clock::now();
+        int rc = BBFG_OK;
+        {
+            std::lock_guard<std::recursive_mutex> clk(ctx->mu);
+            for (auto& j : admitted) {
+                j->cc = std::make_unique<CCJob>();
+                rc = cc_job_init(*ctx, *j->cc, j->U.data(), false, j->m, j->occ.data(), j->n_samples, j->loss,
+                                 j->seed);
+                if (rc != BBFG_OK) break;
+                for (int s = 0; s < j->n_samples; ++s) cc_start_sample(*j->cc, s);
+                active.push_back(j);
+            }
+            if (rc == BBFG_OK) {
+                std::vector<ActiveSample> act;
+                for (auto& j : active)
+                    for (int s = 0; s < j->n_samples; ++s)
+                        if (j->cc->n > 0 && j->cc->samples[(size_t)s].k <= j->cc->n) act.push_back({j->cc.get(), s});
+                if (!act.empty()) rc = cc_step(*ctx, act, nullptr, nullptr);
+            }
+        }
+        if (rc != BBFG_OK) {
+            for (auto& j : admitted)
+                if (!j->cc || std::find(active.begin(), active.end(), j) == active.end()) active.push_back(j);
+            fail_active(rc, last_error());
+            continue;
+        }
+        const double busy = std::chrono::duration<double>(Clock::now() - t0).count();
+        std::lock_guard<std::mutex> lk(mu);
+        st.busy_s += busy;
+        st.iterations++;
+        std::vector<std::shared_ptr<SJob>> keep;
+        for (auto& j : active) {
+            const bool done = j->cc->n == 0 || j->cc->finished == j->n_samples;
+            if (!done) {
+                keep.push_back(j);
+                continue;
+            }
+            j->out = j->cc->out;
+            j->cc.reset();
+            j->state = 2;
+            j->t_done = Clock::now();
+            used -= j->footprint;
+            --outstanding;
+            st.jobs_done++;
+            st.samples_done += (uint64_t)j->n_samples;
+        }
+        active.swap(keep);
+        cv_done.notify_all();
+    }
+}
+
+extern "C" {
+
+int bs_server_create(size_t hbm_budget_bytes, int32_t max_active_jobs, bbfg_server** srv)
+{
+    if (!srv) return set_error(BBFG_EINVAL, "srv is NULL");
+    if (max_active_jobs < 1) return set_error(BBFG_EINVAL, "max_active_jobs < 1");
+    Context* c = nullptr;
+    BBFG_TRY(get_context(&c));
+    auto s = std::make_unique<bbfg_server>();
+    s->ctx = c;
+    s->device = c->device;
+    s->max_active = max_active_jobs;
+    if (hbm_budget_bytes == 0) {
+        size_t freeb = 0, total = 0;
+        BBFG_HIP(hipMemGetInfo(&freeb, &total));
+        hbm_budget_bytes = total / 4;
+    }
+    s->budget = hbm_budget_bytes;
+    BBFG_HIP(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
+    bbfg_server* raw = s.get();
+    s->worker = std::thread([raw] { raw->run(); });
+    *srv = s.release();
+    return BBFG_OK;
+}
+
+int bs_server_submit(bbfg_server* srv, const bbfg_c128* U, int32_t m, const int32_t* input_occupation,
+                     int32_t n_samples, double loss, uint64_t seed, uint64_t* job_id)
+{
+    if (!srv || !job_id) return set_error(BBFG_EINVAL, "NULL argument");
+    BBFG_TRY(cc_validate(U, m, input_occupation, n_samples, loss));
+    auto j = std::make_shared<SJob>();
+    j->m = m;
+    j->U.resize(2 * (size_t)m * (size_t)m);
+    if (is_device_ptr(U)) {
+        BBFG_HIP(hipMemcpy(j->U.data(), U, sizeof(double) * j->U.size(), hipMemcpyDeviceToHost));
+    } else {
+        std::memcpy(j->U.data(), U, sizeof(double) * j->U.size());
+    }
+    j->occ.assign(input_occupation, input_occupation + m);
+    int n = 0;
+    for (int i = 0; i < m; ++i) n += input_occupation[i];
+    j->n_samples = n_samples;
+    j->loss = loss;
+    j->seed = seed;
+    j->footprint = cc_job_footprint(m, n, n_samples, loss);
+    j->t_submit = Clock::now();
+    std::lock_guard<std::mutex> lk(srv->mu);
+    j->id = srv->next_id++;
+    srv->jobs[j->id] = j;
+    srv->queue.push_back(j);
+    srv->outstanding++;
+    srv->st.jobs_submitted++;
+    if (srv->queue.size() > srv->st.max_queued) srv->st.max_queued = srv->queue.size();
+    *job_id = j->id;
+    srv->cv_work.notify_one();
+    return BBFG_OK;
+}
+
+int bs_server_poll(bbfg_server* srv, uint64_t job_id, int32_t* out_occupation, double* latency_s)
+{
+    if (!srv) return set_error(BBFG_EINVAL, "srv is NULL");
+    std::lock_guard<std::mutex> lk(srv->mu);
+    auto it = srv->jobs.find(job_id);
+    if (it == srv->jobs.end()) return set_error(BBFG_ENOTFOUND, "unknown job %llu", (unsigned long long)job_id);
+    auto j = it->second;
+    if (j->state == 0 || j->state == 1) return set_error(BBFG_EBUSY, "job %llu not finished", (unsigned long long)job_id);
+    if (j->state == 3) {
+        srv->jobs.erase(it);
+        return set_error(j->err_code ? j->err_code : BBFG_EDEVICE, "job failed: %s", j->err.c_str());
+    }
+    if (j->n_samples > 0 && !out_occupation) return set_error(BBFG_EINVAL, "out_occupation is NULL");
+    if (j->n_samples > 0) std::memcpy(out_occupation, j->out.data(), sizeof(int32_t) * j->out.size());
+    if (latency_s) *latency_s = std::chrono::duration<double>(j->t_done - j->t_submit).count();
+    srv->jobs.erase(it);
+    return BBFG_OK;
+}
+
+int bs_server_drain(bbfg_server* srv)
+{
+    if (!srv) return set_error(BBFG_EINVAL, "srv is NULL");
+    std::unique_lock<std::mutex> lk(srv->mu);
+    srv->cv_done.wait(lk, [srv] { return srv->outstanding == 0; });
+    return BBFG_OK;
+}
+
+int bs_server_stats(bbfg_server* srv, bbfg_server_stats* out)
+{
+    if (!srv || !out) return set_error(BBFG_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(srv->mu);
+    *out = srv->st;
+    return BBFG_OK;
+}
+
+int bs_server_destroy(bbfg_server* srv)
+{
+    if (!srv) return set_error(BBFG_EINVAL, "srv is NULL");
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->stop = true;
+        srv->cv_work.notify_all();
+    }
+    if (srv->worker.joinable()) srv->worker.join();
+    if (srv->stream) (void)hipStreamDestroy(srv->stream);
+    delete srv;
+    return BBFG_OK;
+}
+
+}  // extern "C"

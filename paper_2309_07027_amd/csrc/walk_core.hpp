@@ -1,0 +1,248 @@
+// walk_core.hpp -- per-lane core of the generalized BB/FG walk
+// (arXiv:2309.07027, Eq. bbfgrepeated walked as in Sec. 2.1/2.2).
+//
+// This header is compiled twice:
+//   * by hipcc for gfx950 (walk.hip): uniform tables are read through the
+//     constant address space, so the compiler turns them into scalar loads and
+//     SGPR operands;
+//   * by a host C++ compiler for the CPU emulation used in tests: the same code
+//     runs one lane at a time with bounds-checked pointers.
+// Floating-point operations are spelled out (explicit fused multiply-adds, the
+// sources are built with -ffp-contract=off), so both builds round identically.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+
+#include "internal.hpp"
+
+#if defined(__HIPCC__)
+#include <hip/hip_runtime.h>
+#define BBFG_FN __device__ __forceinline__
+namespace bbfg {
+template <typename T>
+using kptr = const __attribute__((address_space(4))) T*;
+template <typename T>
+BBFG_FN kptr<T> kconst(const T* p)
+{
+    return (kptr<T>)p;
+}
+BBFG_FN uint32_t uniform_u32(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+}  // namespace bbfg
+#else
+#define BBFG_FN inline
+#include "emu_ptr.hpp"
+#endif
+
+namespace bbfg {
+
+// ---------------------------------------------------------------------------
+// double-double helpers (Knuth TwoSum, Dekker FastTwoSum)
+// ---------------------------------------------------------------------------
+struct ddv {
+    double hi, lo;
+};
+
+BBFG_FN ddv dd_two_sum(double a, double b)
+{
+    double s = a + b;
+    double bb = s - a;
+    double e = (a - (s - bb)) + (b - bb);
+    return {s, e};
+}
+
+BBFG_FN ddv dd_fast(double a, double b)
+{
+    double s = a + b;
+    return {s, b - (s - a)};
+}
+
+BBFG_FN ddv dd_add(ddv a, ddv b)
+{
+    ddv s = dd_two_sum(a.hi, b.hi);
+    ddv t = dd_two_sum(a.lo, b.lo);
+    s.lo += t.hi;
+    s = dd_fast(s.hi, s.lo);
+    s.lo += t.lo;
+    return dd_fast(s.hi, s.lo);
+}
+
+// fused multiply-add in the precision of the operands
+BBFG_FN float fmar(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+BBFG_FN double fmar(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// ---------------------------------------------------------------------------
+// product of N complex column sums: four independent chains, then a tree
+// ---------------------------------------------------------------------------
+template <int N, typename Real>
+BBFG_FN void cprod(const Real* re, const Real* im, Real& pr, Real& pi)
+{
+    constexpr int C = N >= 12 ? 4 : (N >= 4 ? 2 : 1);
+    Real cr[C], ci[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        cr[c] = re[c];
+        ci[c] = im[c];
+    }
+#pragma unroll
+    for (int j = C; j < N; ++j) {
+        const int c = j % C;
+        const Real t0 = ci[c] * im[j];
+        const Real t1 = ci[c] * re[j];
+        const Real nr = fmar(cr[c], re[j], -t0);
+        const Real ni = fmar(cr[c], im[j], t1);
+        cr[c] = nr;
+        ci[c] = ni;
+    }
+#pragma unroll
+    for (int s = 1; s < C; s *= 2) {
+#pragma unroll
+        for (int c = 0; c + s < C; c += 2 * s) {
+            const Real t0 = ci[c] * ci[c + s];
+            const Real t1 = ci[c] * cr[c + s];
+            const Real nr = fmar(cr[c], cr[c + s], -t0);
+            const Real ni = fmar(cr[c], ci[c + s], t1);
+            cr[c] = nr;
+            ci[c] = ni;
+        }
+    }
+    pr = cr[0];
+    pi = ci[0];
+}
+
+// (x / stride) % radix for a 64-bit x; 32-bit arithmetic when x fits.
+BBFG_FN uint32_t digit_of(uint64_t x, uint32_t stride, uint32_t radix)
+{
+    if ((x >> 32) == 0) {
+        const uint32_t x32 = (uint32_t)x;
+        return (x32 / stride) % radix;
+    }
+    return (uint32_t)((x / stride) % radix);
+}
+
+template <typename Real>
+struct RowsOf;
+template <>
+struct RowsOf<double> {
+    static BBFG_FN const double* a(const WalkArgs& A) { return A.a; }
+    static BBFG_FN const double* a2(const WalkArgs& A) { return A.a2; }
+};
+template <>
+struct RowsOf<float> {
+    static BBFG_FN const float* a(const WalkArgs& A) { return A.af; }
+    static BBFG_FN const float* a2(const WalkArgs& A) { return A.a2f; }
+};
+
+// Column sums at block h, position t, for the lane with lane index lane_idx;
+// also the lane's weight for its LANE and HIGH digits:
+// w = prod (-1)^Delta C(M', Delta).
+template <int N, typename Real>
+BBFG_FN void seed(const WalkArgs& A, const PermDesc& d, uint32_t lane_idx, uint64_t h, uint32_t t, Real* re,
+                  Real* im, double& w)
+{
+    kptr<RowInfo> ri = kconst(A.rowinfo + d.rowinfo_off);
+    kptr<Real> rows = kconst(RowsOf<Real>::a(A) + 2 * d.a_off);
+    kptr<double> binom = kconst(A.binom);
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        re[j] = Real(0);
+        im[j] = Real(0);
+    }
+    w = 1.0;
+    for (int k = 0; k < d.r; ++k) {
+        RowInfo x;
+        x.base = ri[k].base;
+        x.kind = ri[k].kind;
+        x.radix = ri[k].radix;
+        x.stride = ri[k].stride;
+        x.mp = ri[k].mp;
+        uint32_t delta = 0;
+        if (x.kind == ROW_LANE) {
+            delta = (lane_idx / x.stride) % x.radix;
+        } else if (x.kind == ROW_HIGH) {
+            delta = digit_of(h, x.stride, x.radix);
+        } else if (x.kind == ROW_LOW) {
+            const uint32_t dg = (t / x.stride) % x.radix;
+            const uint32_t q = t / (x.stride * x.radix);
+            delta = (q & 1u) ? (x.radix - 1u - dg) : dg;
+        }
+        if (x.kind == ROW_LANE || x.kind == ROW_HIGH) {
+            const double b = binom[x.mp * kBinomDim + (int)delta];
+            w *= (delta & 1u) ? -b : b;
+        }
+        const Real coef = (Real)(x.base - 2 * (int)delta);
+        kptr<Real> row = rows + 2 * (size_t)k * N;
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            re[j] = fmar(coef, (Real)row[2 * j], re[j]);
+            im[j] = fmar(coef, (Real)row[2 * j + 1], im[j]);
+        }
+    }
+}
+
+// One work unit of permanent d, for one lane: the lane's sum of weighted
+// addends and the sum of their magnitudes (|re| + |im|).
+template <int N, typename Real>
+BBFG_FN void walk_unit(const WalkArgs& A, const PermDesc& d, uint32_t u_local, uint32_t lane, double& out_r,
+                       double& out_i, double& out_a)
+{
+    const uint32_t upg = (uint32_t)d.units_per_group;
+    const uint32_t g = u_local / upg;
+    const uint32_t part = u_local - g * upg;
+    const uint64_t base = d.span / upg;
+    const uint32_t rem = (uint32_t)(d.span - base * upg);
+    uint64_t lin = (uint64_t)part * base + (part < rem ? part : rem);
+    const uint64_t lin1 = lin + base + (part < rem ? 1u : 0u);
+    uint32_t lane_idx = g * kWave + lane;
+    const bool valid = lane_idx < d.lane_product;
+    if (!valid) lane_idx = 0;
+
+    kptr<TabEntry> tab = kconst(A.tab + d.tab_off);
+    kptr<Real> a2 = kconst(RowsOf<Real>::a2(A) + 2 * d.a2_off);
+    const uint32_t Q = d.Q;
+
+    double accr = 0.0, acci = 0.0, acca = 0.0;
+    Real re[N], im[N];
+    while (lin < lin1) {
+        const uint64_t h = lin / Q;
+        const uint32_t t0 = (uint32_t)(lin - h * Q);
+        const uint64_t bend = (h + 1) * (uint64_t)Q;
+        const uint32_t t1 = (uint32_t)(((lin1 < bend) ? lin1 : bend) - h * Q);
+        double w;
+        seed<N, Real>(A, d, lane_idx, h, t0, re, im, w);
+        if (!valid) w = 0.0;
+        double sr, si, sa;
+        {
+            Real pr, pi;
+            cprod<N, Real>(re, im, pr, pi);
+            const double s = tab[t0].s;
+            sr = s * (double)pr;
+            si = s * (double)pi;
+            sa = __builtin_fabs(s) * (__builtin_fabs((double)pr) + __builtin_fabs((double)pi));
+        }
+        for (uint32_t t = t0 + 1; t < t1; ++t) {
+            const uint32_t rowi = uniform_u32(tab[t].row);
+            const double s = tab[t].s;
+            kptr<Real> row = a2 + 2 * (size_t)rowi * N;
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                re[j] += row[2 * j];
+                im[j] += row[2 * j + 1];
+            }
+            Real pr, pi;
+            cprod<N, Real>(re, im, pr, pi);
+            sr = __builtin_fma(s, (double)pr, sr);
+            si = __builtin_fma(s, (double)pi, si);
+            sa = __builtin_fma(__builtin_fabs(s), __builtin_fabs((double)pr) + __builtin_fabs((double)pi), sa);
+        }
+        accr = __builtin_fma(w, sr, accr);
+        acci = __builtin_fma(w, si, acci);
+        acca = __builtin_fma(__builtin_fabs(w), sa, acca);
+        lin += (uint64_t)(t1 - t0);
+    }
+    out_r = accr;
+    out_i = acci;
+    out_a = acca;
+}
+
+}  // namespace bbfg

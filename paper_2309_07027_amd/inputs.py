@@ -93,9 +93,10 @@ def c3(count: int = 4096):
 
 
 def random_instance(rng: np.random.Generator, n: int, m: int = M_MODES, distinct: bool = False):
-    """A random (A, M) of n photons: n columns of a fresh Haar unitary, rows from
-    n photons placed uniformly on m modes (or n distinct rows when ``distinct``)."""
-    u = haar_from_rng(rng, m)
+    """A random (A, M) of n photons: n columns of a fresh Haar unitary (of size
+    max(m, n)), rows from n photons placed uniformly on m modes (or n distinct
+    rows when ``distinct``)."""
+    u = haar_from_rng(rng, max(m, n))
     if distinct:
         rows = np.sort(rng.choice(m, size=n, replace=False))
         mult = np.ones(n, dtype=np.int32)

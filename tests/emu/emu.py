@@ -1,0 +1,38 @@
+"""Build and run the CPU emulation of the permanent kernels (walk_emu.cpp)."""
+import os
+import subprocess
+from pathlib import Path
+
+import numpy as np
+
+HERE = Path(__file__).resolve().parent
+ROOT = HERE.parent.parent
+CSRC = ROOT / "paper_2309_07027_amd" / "csrc"
+EXE = HERE / "walk_emu"
+SOURCES = [HERE / "walk_emu.cpp", CSRC / "plan.cpp"]
+HEADERS = list(CSRC.glob("*.hpp")) + [ROOT / "include" / "bbfg.h"]
+CMD = ["g++", "-O1", "-g", "-std=c++17", "-ffp-contract=off", "-fsanitize=address,undefined",
+       "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", "-Wall", "-Wno-unknown-pragmas",
+       f"-I{CSRC}", f"-I{ROOT / 'include'}", *map(str, SOURCES), "-o", str(EXE)]
+
+
+def build():
+    newest = max(p.stat().st_mtime for p in SOURCES + HEADERS)
+    if not EXE.exists() or EXE.stat().st_mtime < newest:
+        subprocess.run(CMD, check=True)
+    return EXE
+
+
+def run(A, M, slots: int, f32: bool = False):
+    """Emulated perm_bbfg: (value, rel_err_est, kappa, units)."""
+    A = np.ascontiguousarray(np.asarray(A, dtype=np.complex128))
+    r, n = A.shape
+    lines = [f"{r} {n} {int(slots)} {1 if f32 else 0}", " ".join(str(int(m)) for m in M)]
+    lines.append(" ".join(f"{float(x.real).hex()} {float(x.imag).hex()}" for x in A.ravel()))
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0")
+    p = subprocess.run([str(EXE)], input="\n".join(lines) + "\n", capture_output=True, text=True, env=env,
+                       timeout=600)
+    if p.returncode != 0:
+        raise RuntimeError(f"walk_emu failed ({p.returncode}): {p.stderr[-2000:]}")
+    re_, im_, err, kappa, units = p.stdout.split()
+    return complex(float.fromhex(re_), float.fromhex(im_)), float.fromhex(err), float.fromhex(kappa), int(units)

@@ -1,0 +1,209 @@
+// walk_emu.cpp -- CPU emulation of the permanent kernels, for tests.
+//
+// Runs the SAME per-lane code as the gfx950 walk kernel (walk_core.hpp, here
+// compiled for the host with bounds-checked pointers), one lane at a time, on
+// the work split of the host planner (plan.cpp), and then reproduces the
+// kernel's wavefront butterfly and the finalize kernel's fixed-order
+// double-double sum.  Built with AddressSanitizer/UBSan by the tests.  Because
+// every floating-point operation is written out (no contraction), the result
+// is expected to match the GPU bit for bit.
+//
+// stdin : n_rows n slots f32 / n_rows multiplicities / n_rows*n complex entries
+//         (re im, hex floats), row-major
+// stdout: re im rel_err_est kappa units   (hex floats, then an integer)
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "plan.hpp"
+#include "walk_core.hpp"
+
+using namespace bbfg;
+
+namespace {
+
+template <int NMIN, int NMAX, typename Real>
+void run_unit(const WalkArgs& W, const PermDesc& d, uint32_t u, uint32_t lane, double& r, double& i, double& a)
+{
+    if constexpr (NMIN <= NMAX) {
+        if (d.n == NMIN) walk_unit<NMIN, Real>(W, d, u, lane, r, i, a);
+        else run_unit<NMIN + 1, NMAX, Real>(W, d, u, lane, r, i, a);
+    }
+}
+
+int read_case(int& n_rows, int& n, long long& slots, int& f32, std::vector<int32_t>& M, std::vector<double>& A)
+{
+    if (std::scanf("%d %d %lld %d", &n_rows, &n, &slots, &f32) != 4) return 1;
+    M.resize((size_t)n_rows);
+    for (int i = 0; i < n_rows; ++i)
+        if (std::scanf("%d", &M[(size_t)i]) != 1) return 1;
+    A.resize(2 * (size_t)n_rows * (size_t)n);
+    for (size_t i = 0; i < A.size(); ++i)
+        if (std::scanf("%la", &A[i]) != 1) return 1;
+    return 0;
+}
+
+template <typename Real>
+int emulate(int n_rows, int n, long long slots, const std::vector<int32_t>& M, const std::vector<double>& A)
+{
+    const int f32 = sizeof(Real) == 4 ? 1 : 0;
+    HostPlan P;
+    std::string err;
+    int rc = build_plan(M.data(), n_rows, n, (uint64_t)slots, PlanParams(), P, err);
+    if (rc) {
+        std::fprintf(stderr, "plan error %d: %s\n", rc, err.c_str());
+        return 2;
+    }
+    if (n == 0) {
+        std::printf("%a %a %a %a %d\n", 1.0, 0.0, 0.0, 1.0, 0);
+        return 0;
+    }
+    const int r = P.r;
+    // arena exactly as the prep kernel lays it out: r x n rows, then 2r x n +-2a rows
+    std::vector<Real> arena(2 * (size_t)r * (size_t)n * 3);
+    for (int k = 0; k < r; ++k)
+        for (int j = 0; j < n; ++j) {
+            const double xr = A[2 * ((size_t)P.src_row[(size_t)k] * n + j)];
+            const double xi = A[2 * ((size_t)P.src_row[(size_t)k] * n + j) + 1];
+            const size_t da = (size_t)k * n + j;
+            const size_t dp = (size_t)r * n + (size_t)(2 * k) * n + j;
+            const size_t dm = dp + (size_t)n;
+            const Real fr = (Real)xr, fi = (Real)xi;
+            arena[2 * da] = fr;
+            arena[2 * da + 1] = fi;
+            arena[2 * dp] = (Real)2 * fr;
+            arena[2 * dp + 1] = (Real)2 * fi;
+            arena[2 * dm] = (Real)-2 * fr;
+            arena[2 * dm + 1] = (Real)-2 * fi;
+        }
+    std::vector<double> binom((size_t)kBinomDim * kBinomDim);
+    for (int m = 0; m < kBinomDim; ++m)
+        for (int k = 0; k < kBinomDim; ++k) {
+            double v;
+            if (k > m) v = 0.0;
+            else if (k == 0 || k == m) v = 1.0;
+            else v = binom[(size_t)(m - 1) * kBinomDim + k - 1] + binom[(size_t)(m - 1) * kBinomDim + k];
+            binom[(size_t)m * kBinomDim + k] = v;
+        }
+    PermDesc d;
+    std::memset(&d, 0, sizeof d);
+    d.a_off = 0;
+    d.a2_off = (uint64_t)r * n;
+    d.tab_off = 0;
+    d.unit_base = 0;
+    d.units = P.units;
+    d.units_per_group = P.units_per_group;
+    d.span = P.span;
+    d.rowinfo_off = 0;
+    d.n = n;
+    d.r = r;
+    d.Q = P.Q;
+    d.lane_product = P.lane_product;
+    d.groups = P.groups;
+    d.scale = std::ldexp(1.0, 1 - n);
+    d.err_coeff = P.err_coeff * (f32 ? 0x1.0p-24 : 0x1.0p-53);
+
+    WalkArgs W;
+    std::memset(&W, 0, sizeof W);
+    W.rowinfo = P.rows.data();
+    W.tab = P.table.data();
+    W.binom = binom.data();
+    if (f32) {
+        W.af = reinterpret_cast<const float*>(arena.data());
+        W.a2f = W.af;
+    } else {
+        W.a = reinterpret_cast<const double*>(arena.data());
+        W.a2 = W.a;
+    }
+    emu_clear();
+    emu_register(P.rows.data(), sizeof(RowInfo) * P.rows.size());
+    emu_register(P.table.data(), sizeof(TabEntry) * P.table.size());
+    emu_register(binom.data(), sizeof(double) * binom.size());
+    emu_register(arena.data(), sizeof(Real) * arena.size());
+
+    std::vector<double> part((size_t)P.units * kPartialDoubles);
+    for (uint64_t u = 0; u < P.units; ++u) {
+        ddv sr[kWave], si[kWave];
+        double sa[kWave];
+        for (uint32_t lane = 0; lane < (uint32_t)kWave; ++lane) {
+            double x = 0, y = 0, z = 0;
+            run_unit<1, kMaxN, Real>(W, d, (uint32_t)u, lane, x, y, z);
+            sr[lane] = {x, 0.0};
+            si[lane] = {y, 0.0};
+            sa[lane] = z;
+        }
+        for (int off = 1; off < kWave; off <<= 1) {
+            ddv nr[kWave], ni[kWave];
+            double na[kWave];
+            for (int l = 0; l < kWave; ++l) {
+                nr[l] = dd_add(sr[l], sr[l ^ off]);
+                ni[l] = dd_add(si[l], si[l ^ off]);
+                na[l] = sa[l] + sa[l ^ off];
+            }
+            for (int l = 0; l < kWave; ++l) {
+                sr[l] = nr[l];
+                si[l] = ni[l];
+                sa[l] = na[l];
+            }
+        }
+        double* p = part.data() + u * kPartialDoubles;
+        p[0] = sr[0].hi;
+        p[1] = sr[0].lo;
+        p[2] = si[0].hi;
+        p[3] = si[0].lo;
+        p[4] = sa[0];
+    }
+    constexpr int T = 256;
+    std::vector<double> sh(T * 5);
+    for (int t = 0; t < T; ++t) {
+        ddv r2 = {0.0, 0.0}, i2 = {0.0, 0.0};
+        double a2 = 0.0;
+        for (uint64_t u = (uint64_t)t; u < P.units; u += T) {
+            const double* p = part.data() + u * kPartialDoubles;
+            r2 = dd_add(r2, {p[0], p[1]});
+            i2 = dd_add(i2, {p[2], p[3]});
+            a2 += p[4];
+        }
+        sh[(size_t)t * 5 + 0] = r2.hi;
+        sh[(size_t)t * 5 + 1] = r2.lo;
+        sh[(size_t)t * 5 + 2] = i2.hi;
+        sh[(size_t)t * 5 + 3] = i2.lo;
+        sh[(size_t)t * 5 + 4] = a2;
+    }
+    for (int s = T / 2; s > 0; s >>= 1)
+        for (int t = 0; t < s; ++t) {
+            double* m = sh.data() + (size_t)t * 5;
+            const double* o = sh.data() + (size_t)(t + s) * 5;
+            ddv x = dd_add({m[0], m[1]}, {o[0], o[1]});
+            ddv y = dd_add({m[2], m[3]}, {o[2], o[3]});
+            m[0] = x.hi;
+            m[1] = x.lo;
+            m[2] = y.hi;
+            m[3] = y.lo;
+            m[4] = m[4] + o[4];
+        }
+    const double re = (sh[0] + sh[1]) * d.scale;
+    const double im = (sh[2] + sh[3]) * d.scale;
+    const double mag = std::sqrt(re * re + im * im);
+    const double absum = sh[4] * d.scale;
+    const double kappa = mag > 0.0 ? absum / mag : INFINITY;
+    std::printf("%a %a %a %a %llu\n", re, im, kappa * d.err_coeff, kappa, (unsigned long long)P.units);
+    return 0;
+}
+
+}  // namespace
+
+int main()
+{
+    int n_rows = 0, n = 0, f32 = 0;
+    long long slots = 0;
+    std::vector<int32_t> M;
+    std::vector<double> A;
+    if (read_case(n_rows, n, slots, f32, M, A)) {
+        std::fprintf(stderr, "bad input\n");
+        return 2;
+    }
+    return f32 ? emulate<float>(n_rows, n, slots, M, A) : emulate<double>(n_rows, n, slots, M, A);
+}

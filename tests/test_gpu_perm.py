@@ -1,0 +1,238 @@
+"""GPU parity of the generalized BB/FG permanent (perm_bbfg, perm_batch) against
+the double-double CPU oracle, through the C ABI.
+
+Tolerance: relative error <= 1e-10 (Eq. relative_error of Sec. 3.2) for the
+FP64 path, on every case.  The FP32 path reports its error against the oracle.
+"""
+import json
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2309_07027_amd import binding as B
+from paper_2309_07027_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "perm_golden.json")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    return abs(a - b) / abs(b)
+
+
+def expand(A, M):
+    return np.repeat(A, M, axis=0)
+
+
+def rand_instance(rng, n, kind):
+    if kind == "distinct":
+        return I.random_instance(rng, n, distinct=True)
+    if kind == "bunched":
+        return I.random_instance(rng, n, m=max(2, n // 2))
+    return I.random_instance(rng, n)
+
+
+def load_golden():
+    with open(GOLDEN) as fh:
+        g = json.load(fh)
+    out = {}
+    for c in g["cases"]:
+        A = np.array([complex(a, b) for a, b in c["A"]]).reshape(c["rows"], c["cols"])
+        val = complex(c["re"][0] + c["re"][1], c["im"][0] + c["im"][1])
+        out[c["name"]] = (A, np.array(c["M"], dtype=np.int32), val, c)
+    return out
+
+
+@pytest.fixture(scope="module")
+def golden():
+    return load_golden()
+
+
+def test_c1_n20_vs_oracle(oracle):
+    A, M = I.c1()
+    say("case c1 n=20")
+    got, info = B.perm_bbfg(A, M, with_info=True)
+    ref = oracle.perm_glynn_gray(A)
+    assert rel(got, ref) <= TOL
+    assert info["n_addends"] == 2 ** 19
+    assert 0 < info["rel_err_est"] < 1e-10
+    assert info["kappa"] > 1
+
+
+@pytest.mark.parametrize("kind", ["distinct", "bunched", "random"])
+def test_random_small_vs_oracle(oracle, kind):
+    rng = np.random.default_rng({"distinct": 1, "bunched": 2, "random": 3}[kind])
+    for n in list(range(1, 15)) + [16, 18]:
+        A, M = rand_instance(rng, n, kind)
+        say(f"case {kind} n={n} M={M.tolist()}")
+        got = B.perm_bbfg(A, M)
+        ref = oracle.perm_generalized(A, M)
+        assert rel(got, ref) <= TOL, (n, M)
+
+
+def test_closed_forms_on_gpu():
+    # J_n sums 2^{n-1} addends of size up to n^n with heavy cancellation
+    # (kappa ~ 5e2 at n = 20), so the FP64 bar applies, not bit-exactness.
+    for n in (1, 2, 5, 10, 20):
+        J = np.ones((n, n), dtype=complex)
+        v, info = B.perm_bbfg(J, with_info=True)
+        e = rel(v, math.factorial(n))
+        assert e <= TOL and e <= max(info["rel_err_est"], 1e-15)
+        assert rel(B.perm_bbfg(np.eye(n, dtype=complex)), 1.0) <= 1e-14
+    # one row of ones repeated n times: perm = n!
+    for n in (3, 12, 30, 48):
+        assert rel(B.perm_bbfg(np.ones((1, n), dtype=complex), [n]), math.factorial(n)) <= TOL
+    D10 = 1334961
+    assert rel(B.perm_bbfg(np.ones((10, 10)) - np.eye(10) + 0j), D10) <= TOL
+    rng = np.random.default_rng(5)
+    u = rng.standard_normal(12) + 1j * rng.standard_normal(12)
+    v = rng.standard_normal(12) + 1j * rng.standard_normal(12)
+    assert rel(B.perm_bbfg(np.outer(u, v)), math.factorial(12) * np.prod(u) * np.prod(v)) <= 1e-12
+
+
+def test_edge_cases(oracle):
+    rng = np.random.default_rng(8)
+    # rows with zero multiplicity are ignored
+    A = rng.standard_normal((5, 6)) + 1j * rng.standard_normal((5, 6))
+    M = np.array([2, 0, 3, 0, 1], dtype=np.int32)
+    assert rel(B.perm_bbfg(A, M), oracle.perm_bruteforce(expand(A, M))) <= TOL
+    # no row of multiplicity one: the pivot keeps M - 1 free copies
+    M = np.array([2, 0, 2, 0, 2], dtype=np.int32)
+    assert rel(B.perm_bbfg(A, M), oracle.perm_bruteforce(expand(A, M))) <= TOL
+    # a single row repeated n times (one digit only)
+    a = rng.standard_normal((1, 9)) + 1j * rng.standard_normal((1, 9))
+    assert rel(B.perm_bbfg(a, [9]), oracle.perm_generalized(a, [9])) <= TOL
+    # fewer addends than lanes, and sums that leave lanes idle
+    for M in ([1, 1], [1, 2], [2, 2, 2], [1, 1, 1, 1, 1, 2], [4, 3]):
+        n = sum(M)
+        A = rng.standard_normal((len(M), n)) + 1j * rng.standard_normal((len(M), n))
+        assert rel(B.perm_bbfg(A, M), oracle.perm_generalized(A, M)) <= TOL, M
+
+
+def test_largest_size_n48(oracle):
+    # n = 48 (BBFG_MAX_N) with multiplicities that keep C' small enough for the oracle
+    rng = np.random.default_rng(48)
+    u = I.haar_from_rng(rng, 60)
+    M = np.array([6] * 8, dtype=np.int32)
+    A = np.ascontiguousarray(u[:8, :48])
+    say("case n=48 M=6^8")
+    got, info = B.perm_bbfg(A, M, with_info=True)
+    ref, absum = oracle.perm_generalized(A, M, with_abs=True)
+    say(f"  kappa {absum / abs(ref):.2e}, rel err {rel(got, ref):.2e}, estimate {info['rel_err_est']:.2e}")
+    assert rel(got, ref) <= TOL
+    assert rel(got, ref) <= info["rel_err_est"]
+
+
+def test_row_order_and_pivot_invariance(oracle):
+    rng = np.random.default_rng(9)
+    A, M = I.random_instance(rng, 14, m=8)
+    ref = oracle.perm_generalized(A, M)
+    for t in range(4):
+        p = rng.permutation(len(M))
+        assert rel(B.perm_bbfg(A[p].copy(), M[p]), ref) <= TOL
+
+
+def test_transpose_invariance_gpu():
+    rng = np.random.default_rng(10)
+    A = rng.standard_normal((16, 16)) + 1j * rng.standard_normal((16, 16))
+    assert rel(B.perm_bbfg(A.T.copy()), B.perm_bbfg(A)) <= 1e-12
+
+
+def test_c2_full_size_vs_golden(golden):
+    for name in ("c2a", "c2b", "c2c"):
+        A, M, ref, c = golden[name]
+        say(f"case {name} n={A.shape[1]} rows={A.shape[0]}")
+        got, info = B.perm_bbfg(A, M, with_info=True)
+        assert rel(got, ref) <= TOL, name
+        # the reported estimate (kappa * u * (n + sqrt(Q))) is conservative
+        assert rel(got, ref) <= info["rel_err_est"] < 1e-7
+        # inputs regenerate to the stored bytes on this machine (informational)
+        Ag, Mg = getattr(I, name)()
+        say(f"  {name}: rel err {rel(got, ref):.2e}, regenerated inputs identical: {np.array_equal(Ag, A)}")
+
+
+def test_batch_bitwise_equals_single(oracle):
+    rng = np.random.default_rng(11)
+    mats = []
+    for i in range(48):
+        n = int(rng.integers(1, 23))
+        mats.append(rand_instance(rng, n, ["distinct", "bunched", "random"][i % 3]))
+    got = B.perm_batch(mats)
+    for (A, M), g in zip(mats, got):
+        s = B.perm_bbfg(A, M)
+        assert g == s  # same work split, same reduction order: identical bits
+    for (A, M), g in list(zip(mats, got))[:16]:
+        assert rel(g, oracle.perm_generalized(A, M)) <= TOL
+
+
+def test_c3_full_batch(golden):
+    items = I.c3(4096)
+    idx = [int(k.split("_")[1]) for k in golden if k.startswith("c3_")]
+    for i in idx:
+        A, M, _, _ = golden[f"c3_{i}"]
+        items[i] = (A, M)
+    say("case c3 4096 items fp64")
+    out, err = B.perm_batch(items, with_err=True)
+    assert np.isfinite(out).all()
+    for i in idx:
+        assert rel(out[i], golden[f"c3_{i}"][2]) <= TOL, i
+        assert rel(out[i], golden[f"c3_{i}"][2]) <= err[i]
+    say(f"  fp64 error estimates: median {np.median(err):.2e} max {err.max():.2e}")
+    assert (err < 1e-8).all()
+    # FP32 path: error against the FP64 result, reported per item
+    say("case c3 4096 items fp32")
+    out32, err32 = B.perm_batch(items, precision=B.BBFG_FP32, with_err=True)
+    e = np.abs(out32 - out) / np.abs(out)
+    say(f"  fp32 rel err: median {np.median(e):.2e} max {e.max():.2e}; estimate median {np.median(err32):.2e}")
+    assert np.median(e) < 1e-4
+    for i in idx:
+        ref = golden[f"c3_{i}"][2]
+        assert rel(out32[i], ref) < 1e-2
+
+
+def test_device_pointers():
+    import torch
+    A, M = I.c1()
+    At = torch.from_numpy(A).to("cuda")
+    assert B.perm_bbfg(At, M) == B.perm_bbfg(A, M)
+    mats = [I.c3_item(i) for i in range(20)]
+    Ap, ao, nr, Mp, mo, nc = B.pack_batch(mats)
+    outd = torch.zeros(len(mats), dtype=torch.complex128, device="cuda")
+    B.perm_batch_packed(torch.from_numpy(Ap).to("cuda"), ao, nr, Mp, mo, nc, out=outd)
+    host = B.perm_batch(mats)
+    assert np.array_equal(outd.cpu().numpy(), host)
+
+
+def test_repeat_runs_bitwise_identical():
+    A, M = I.c1()
+    vals = {B.perm_bbfg(A, M) for _ in range(3)}
+    assert len(vals) == 1
+
+
+def test_gpu_matches_cpu_emulation_bitwise():
+    # The CPU build of the kernel's per-lane code (tests/emu) with the same work
+    # split must reproduce the GPU result bit for bit: no contraction, the same
+    # fused multiply-adds, the same reduction orders.
+    from tests.emu import emu
+    emu.build()
+    rng = np.random.default_rng(12)
+    cases = [I.c1(), I.random_instance(rng, 16, m=7), I.random_instance(rng, 12, distinct=True)]
+    u = I.haar_from_rng(np.random.default_rng(48), 60)
+    cases.append((np.ascontiguousarray(u[:8, :48]), np.array([6] * 8, dtype=np.int32)))
+    for A, M in cases:
+        n = A.shape[1]
+        waves, ncu = B.walk_occupancy(n)
+        say(f"case emulation n={n} M={M.tolist()} slots={waves * ncu}")
+        g = B.perm_bbfg(A, M)
+        e, _, _, _ = emu.run(A, M, waves * ncu)
+        assert g == e, (n, g, e)
