@@ -18,6 +18,7 @@ own device time, measured with HIP events on the stream it runs on.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -45,6 +46,21 @@ def cprime_of(M):
     return c
 
 
+def measured_traffic():
+    """HBM bytes per launch of the case-(a) walk kernel from the committed rocprofv3
+    counter summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain-copy calibration),
+    or None when the kernel sources changed since the counters were taken."""
+    try:
+        rec = json.loads(open(os.path.join(ROOT, "profiles", "walk_traffic.txt")).read())
+    except (OSError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for p in ("paper_2309_07027_amd/csrc/walk_core.hpp", "paper_2309_07027_amd/csrc/walk.hip"):
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return rec["traffic_bytes_per_launch"] if h.hexdigest()[:16] == rec.get("kernel_source_hash") else None
+
+
 def cpu_baseline(sample_terms: int):
     """The double-double oracle (as is) on the first `sample_terms` addends of (a)."""
     from oracle import oracle as O
@@ -64,10 +80,12 @@ def cpu_baseline(sample_terms: int):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-log2", type=int, default=25)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run one plain device-to-device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the permanent and sampler paths run on a single device "
@@ -81,6 +99,15 @@ def main():
     from paper_2309_07027_amd import inputs as I
 
     torch.cuda.set_device(0)
+    if args.copy_probe_mib:
+        n = args.copy_probe_mib << 20
+        src = torch.ones(n // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": n, "copy_probe_bytes_written": n}), flush=True)
+        return
     B.init()
     inputs = {}
     for c in CASES:
@@ -122,7 +149,7 @@ def main():
     dom = per_case["a"]
     achieved = dom["kernel_tflops"]
     roofline = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": measured_traffic(),
                 "kernel": "walk_single_kernel<30,double> (case a)",
                 "flops_per_launch": dom["flops"], "avg_launch_ms": dom["kernel_ms"]}
     out = {"metric": METRIC, "value": round(value, 3), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
