@@ -138,16 +138,46 @@ int perm_bbfg(const bbfg_c128 *A, int32_t n_rows, const int32_t *row_mult, int32
  *   out              batch bbfg_c128 results, host or device.
  *   rel_err_est      nullable, batch doubles (host): per-result error estimate.
  *
- * Each result is bitwise identical to perm_bbfg on the same matrix with the
- * same precision: the work decomposition of an item depends only on its shape.
+ * Each item's result depends only on that item (its work split is a function of
+ * its shape and the tuned unit length), so it is bitwise identical whatever
+ * else is in the batch; it agrees with perm_bbfg to the stated error, not
+ * necessarily bit for bit (perm_bbfg splits a lone permanent to fill the
+ * device).
  * Errors: as perm_bbfg, per item.
  */
 int perm_batch(int32_t batch, const bbfg_c128 *A_packed, const int64_t *A_offset,
                const int32_t *n_rows, const int32_t *row_mult_packed, const int64_t *row_mult_offset,
                const int32_t *n_cols, int32_t precision, bbfg_c128 *out, double *rel_err_est);
 
-/* Kernel-only device time (ms) of the last perm_batch walk launch on this thread. */
+/* Device time (ms) of the last perm_batch on this thread: the walk kernel when
+ * launched directly, the whole replayed graph otherwise. */
 double perm_batch_last_kernel_ms(void);
+
+/* 1 when the last perm_batch on this thread replayed a captured hipGraph.  A
+ * batch layout (shapes, multiplicities, buffer addresses) seen for the second
+ * time is captured into a graph -- upload, gather, persistent walk, finalize,
+ * download -- and replayed whenever it recurs. */
+int perm_batch_last_was_graph(void);
+
+/*
+ * Batched launches (perm_batch, and the minors of bs_sample and the server)
+ * split each permanent into work units of L Gray positions per lane, with L a
+ * function of the column count only, so an item's result does not depend on the
+ * other items of the batch.  L is chosen by an autotuner that times synthetic
+ * batches of n-photon permanents (photons at random on 60 modes) for
+ * L in {64, ..., 4096} on the current device; untuned n use L = 512.
+ *
+ * bbfg_autotune        tunes n in [n_lo, n_hi] for the given precision; when
+ *                      cache_path is not NULL, writes every tuned entry to it as
+ *                      text lines "precision n L".  Takes ~0.1-1 s per n.
+ * bbfg_autotune_load   loads such a file (also done at initialisation when the
+ *                      environment variable BBFG_AUTOTUNE_CACHE names one).
+ * bbfg_batch_unit_length  the L currently used for n_cols columns.
+ * Errors: BBFG_EINVAL, BBFG_ERANGE, BBFG_EDEVICE.
+ */
+int bbfg_autotune(int32_t n_lo, int32_t n_hi, int32_t precision, const char *cache_path);
+int bbfg_autotune_load(const char *cache_path);
+int bbfg_batch_unit_length(int32_t n_cols, int32_t precision, uint64_t *unit_length);
 
 /*
  * bs_sample -- Clifford & Clifford boson sampling (Sec. 4), ideal or lossy.

@@ -77,6 +77,7 @@ SIGNATURES = {
     "perm_bbfg": (ctypes.c_int, [_P, _I32, _PI32, _I32, _P, ctypes.POINTER(Info)]),
     "perm_batch": (ctypes.c_int, [_I32, _P, _PI64, _PI32, _PI32, _PI64, _PI32, _I32, _P, _PD]),
     "perm_batch_last_kernel_ms": (ctypes.c_double, []),
+    "perm_batch_last_was_graph": (ctypes.c_int, []),
     "bs_sample": (ctypes.c_int, [_P, _I32, _PI32, _I32, ctypes.c_double, ctypes.c_uint64, _PI32,
                                  ctypes.POINTER(Info)]),
     "bs_server_create": (ctypes.c_int, [ctypes.c_size_t, _I32, ctypes.POINTER(_P)]),
@@ -89,6 +90,9 @@ SIGNATURES = {
     "bbfg_plan_query": (ctypes.c_int, [_PI32, _I32, _I32, _I32, ctypes.POINTER(PlanSummary)]),
     "bbfg_gray_table": (ctypes.c_int, [_PI32, _I32, _I32, _PI32, _PI32]),
     "bbfg_walk_occupancy": (ctypes.c_int, [_I32, _I32, _PI32, _PI32]),
+    "bbfg_autotune": (ctypes.c_int, [_I32, _I32, _I32, ctypes.c_char_p]),
+    "bbfg_autotune_load": (ctypes.c_int, [ctypes.c_char_p]),
+    "bbfg_batch_unit_length": (ctypes.c_int, [_I32, _I32, ctypes.POINTER(ctypes.c_uint64)]),
 }
 
 _lib = None
@@ -227,6 +231,10 @@ def batch_last_kernel_ms() -> float:
     return float(lib().perm_batch_last_kernel_ms())
 
 
+def batch_last_was_graph() -> bool:
+    return bool(lib().perm_batch_last_was_graph())
+
+
 def bs_sample(U, input_occupation, n_samples: int, loss: float = 0.0, seed: int = 0, with_info: bool = False):
     """Clifford & Clifford samples: (n_samples, m) int32 output occupations."""
     ptr, keep, shape = _cmat_ptr(U)
@@ -305,6 +313,22 @@ def gray_table(radices):
     dr = np.zeros(n, dtype=np.int32)
     _check(lib().bbfg_gray_table(pr, len(r), n, ch.ctypes.data_as(_PI32), dr.ctypes.data_as(_PI32)))
     return ch, dr
+
+
+def autotune(n_lo: int, n_hi: int, precision: int = BBFG_FP64, cache_path: str | None = None):
+    """Tune the batched unit length for n in [n_lo, n_hi] on this device."""
+    _check(lib().bbfg_autotune(int(n_lo), int(n_hi), int(precision),
+                               None if cache_path is None else str(cache_path).encode()))
+
+
+def autotune_load(cache_path: str):
+    _check(lib().bbfg_autotune_load(str(cache_path).encode()))
+
+
+def batch_unit_length(n_cols: int, precision: int = BBFG_FP64) -> int:
+    L = ctypes.c_uint64()
+    _check(lib().bbfg_batch_unit_length(int(n_cols), int(precision), ctypes.byref(L)))
+    return L.value
 
 
 def walk_occupancy(n_cols: int, precision: int = BBFG_FP64):

@@ -1,0 +1,144 @@
+// autotune.cpp -- unit length of batched launches, tuned on the device.
+//
+// A batched launch splits every permanent into units of L Gray positions per
+// lane (one wavefront each).  Short units cost re-seeding and reductions;
+// long units leave wavefronts idle at the end of the launch.  The best L
+// depends on the column count n (seeding costs O(r n), a step O(n)), so it is
+// tuned per n: a synthetic batch of n-photon permanents (photons placed at
+// random on 60 modes, as in the sampling workloads) is timed for each
+// candidate L and the fastest per addend is kept.  Untuned n use a default.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "runtime.hpp"
+#include "sampler.hpp"
+
+using namespace bbfg;
+
+namespace {
+
+const uint64_t kCandidates[] = {64, 128, 256, 512, 1024, 2048, 4096};
+
+// Synthetic batch: `count` items of n photons on 60 modes; entries of modulus
+// 1/sqrt(n) with pseudo-random phases (the values do not affect the timing).
+void synthetic_batch(int n, int count, uint64_t seed, std::vector<double>& A, std::vector<int64_t>& aoff,
+                     std::vector<int32_t>& rows, std::vector<int32_t>& mult, std::vector<int64_t>& moff)
+{
+    constexpr int kModes = 60;
+    A.clear();
+    aoff.clear();
+    rows.clear();
+    mult.clear();
+    moff.clear();
+    uint64_t c = 0;
+    for (int it = 0; it < count; ++it) {
+        int cnt[kModes] = {0};
+        for (int p = 0; p < n; ++p) cnt[(splitmix64_draw(seed, c++) >> 32) % kModes]++;
+        aoff.push_back((int64_t)A.size() / 2);
+        moff.push_back((int64_t)mult.size());
+        int r = 0;
+        for (int k = 0; k < kModes; ++k)
+            if (cnt[k]) {
+                mult.push_back(cnt[k]);
+                ++r;
+                for (int j = 0; j < n; ++j) {
+                    const double ph = (double)(splitmix64_draw(seed, c++) >> 11) * 0x1.0p-53 * 6.283185307179586;
+                    A.push_back(std::cos(ph) / std::sqrt((double)n));
+                    A.push_back(std::sin(ph) / std::sqrt((double)n));
+                }
+            }
+        rows.push_back(r);
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int bbfg_autotune(int32_t n_lo, int32_t n_hi, int32_t precision, const char* cache_path)
+{
+    const int f32 = precision == BBFG_FP32 ? 1 : 0;
+    if (precision != BBFG_FP64 && precision != BBFG_FP32) return set_error(BBFG_EINVAL, "bad precision");
+    const int max_n = f32 ? kMaxNF32 : kMaxN;
+    if (n_lo < 1 || n_hi < n_lo || n_hi > max_n) return set_error(BBFG_ERANGE, "n range [%d, %d] invalid", n_lo, n_hi);
+    Context* c = nullptr;
+    BBFG_TRY(get_context(&c));
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    hipStream_t s = current_stream();
+    for (int n = n_lo; n <= n_hi; ++n) {
+        std::vector<double> A;
+        std::vector<int64_t> aoff, moff;
+        std::vector<int32_t> rows, mult;
+        const int count = 256;
+        synthetic_batch(n, count, 0x5eedULL * (uint64_t)n, A, aoff, rows, mult, moff);
+        DevBuf dA;
+        BBFG_TRY(dA.ensure(sizeof(double) * A.size()));
+        BBFG_HIP(hipMemcpyAsync(dA.p, A.data(), sizeof(double) * A.size(), hipMemcpyHostToDevice, s));
+        BBFG_HIP(hipStreamSynchronize(s));
+        double best_rate = -1.0;
+        uint64_t best_L = kDefaultBatchUnit;
+        for (uint64_t L : kCandidates) {
+            c->batch_L[std::make_pair(n, f32)] = L;
+            std::vector<PermItem> items((size_t)count);
+            uint64_t addends = 0;
+            for (int i = 0; i < count; ++i) {
+                PermItem& it = items[(size_t)i];
+                it.src = dA.as<double>();
+                it.src_off = (uint64_t)aoff[(size_t)i];
+                it.ld = (uint32_t)n;
+                it.n_rows = rows[(size_t)i];
+                it.n = n;
+                it.mult = mult.data() + moff[(size_t)i];
+                BBFG_TRY(get_plan(*c, it.mult, it.n_rows, n, f32, PLAN_BATCH, &it.plan));
+                addends += it.plan->n_addends;
+            }
+            double ms_best = 1e300;
+            for (int rep = 0; rep < 3; ++rep) {
+                RunResult rr;
+                BBFG_TRY(run_perms(*c, items, f32, false, nullptr, nullptr, &rr));
+                ms_best = std::min(ms_best, rr.kernel_ms);
+            }
+            const double rate = (double)addends / ms_best;
+            if (rate > best_rate * 1.02) {  // prefer shorter units unless a longer one is clearly faster
+                best_rate = rate;
+                best_L = L;
+            }
+        }
+        c->batch_L[std::make_pair(n, f32)] = best_L;
+        dA.release();
+    }
+    if (cache_path) {
+        FILE* f = std::fopen(cache_path, "w");
+        if (!f) return set_error(BBFG_EINVAL, "cannot write %s", cache_path);
+        for (auto& kv : c->batch_L)
+            std::fprintf(f, "%d %d %llu\n", kv.first.second, kv.first.first, (unsigned long long)kv.second);
+        std::fclose(f);
+    }
+    return BBFG_OK;
+}
+
+int bbfg_autotune_load(const char* cache_path)
+{
+    if (!cache_path) return set_error(BBFG_EINVAL, "cache_path is NULL");
+    Context* c = nullptr;
+    BBFG_TRY(get_context(&c));
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    return load_autotune_file(*c, cache_path);
+}
+
+int bbfg_batch_unit_length(int32_t n_cols, int32_t precision, uint64_t* unit_length)
+{
+    if (!unit_length) return set_error(BBFG_EINVAL, "unit_length is NULL");
+    const int f32 = precision == BBFG_FP32 ? 1 : 0;
+    if (n_cols < 1 || n_cols > (f32 ? kMaxNF32 : kMaxN)) return set_error(BBFG_ERANGE, "n_cols out of range");
+    Context* c = nullptr;
+    BBFG_TRY(get_context(&c));
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    *unit_length = batch_unit_length(*c, n_cols, f32);
+    return BBFG_OK;
+}
+
+}  // extern "C"

@@ -56,6 +56,7 @@ int device_view(Context& c, const bbfg_c128* A, uint64_t elems, const double** o
 }
 
 thread_local double t_batch_kernel_ms = 0.0;
+thread_local bool t_batch_graph = false;
 
 }  // namespace
 
@@ -104,7 +105,7 @@ int perm_bbfg(const bbfg_c128* A, int32_t n_rows, const int32_t* row_mult, int32
     items[0].n_rows = n_rows;
     items[0].n = n_cols;
     items[0].mult = row_mult;
-    BBFG_TRY(get_plan(*c, row_mult, n_rows, n_cols, 0, &items[0].plan));
+    BBFG_TRY(get_plan(*c, row_mult, n_rows, n_cols, 0, PLAN_SINGLE, &items[0].plan));
     double res[2], diag[2];
     RunResult rr;
     BBFG_TRY(run_perms(*c, items, 0, true, res, diag, &rr));
@@ -164,13 +165,14 @@ int perm_batch(int32_t batch, const bbfg_c128* A_packed, const int64_t* A_offset
             it.n_rows = n_rows[b];
             it.n = n_cols[b];
             it.mult = row_mult_packed + row_mult_offset[b];
-            BBFG_TRY(get_plan(*c, it.mult, it.n_rows, it.n, f32, &it.plan));
+            BBFG_TRY(get_plan(*c, it.mult, it.n_rows, it.n, f32, PLAN_BATCH, &it.plan));
             items.push_back(std::move(it));
             idx.push_back(b);
         }
         std::vector<double> r2(2 * items.size()), d2(2 * items.size());
         RunResult rr;
-        BBFG_TRY(run_perms(*c, items, f32, false, r2.data(), d2.data(), &rr));
+        BBFG_TRY(run_perms(*c, items, f32, false, r2.data(), d2.data(), &rr, true, true));
+        t_batch_graph = rr.graph;
         t_batch_kernel_ms = rr.kernel_ms;
         for (size_t i = 0; i < items.size(); ++i) {
             res[2 * (size_t)idx[i]] = r2[2 * i];
@@ -189,6 +191,8 @@ int perm_batch(int32_t batch, const bbfg_c128* A_packed, const int64_t* A_offset
 }
 
 double perm_batch_last_kernel_ms(void) { return t_batch_kernel_ms; }
+
+int perm_batch_last_was_graph(void) { return t_batch_graph ? 1 : 0; }
 
 int bbfg_plan_query(const int32_t* row_mult, int32_t n_rows, int32_t n_cols, int32_t slots, bbfg_plan_summary* out)
 {

@@ -33,8 +33,11 @@ struct RowInfo {
 // Gray-walk table entry for position t of a block: the +-2a row that is added
 // when stepping from t-1 to t, and the signed low-digit weight at t:
 //   s(t) = prod_{low k} (-1)^{Delta_k(t)} C(M'_k, Delta_k(t)).
+// The planner numbers the kept rows so that low digit i is kept row i; a table
+// then depends on the radices of the low digits only and is shared by every
+// permanent with the same low radices.
 struct TabEntry {
-    uint32_t row;  // index into the 2r x n array of +-2a rows (2k: +2a_k, 2k+1: -2a_k)
+    uint32_t row;  // index into the 2r x n array of +-2a rows (2i: +2a_i, 2i+1: -2a_i)
     uint32_t pad;
     double s;
 };
@@ -43,7 +46,7 @@ struct TabEntry {
 struct PermDesc {
     uint64_t a_off;          // element offset of the r x n kept rows (complex)
     uint64_t a2_off;         // element offset of the 2r x n +-2a rows (complex)
-    uint64_t tab_off;        // entry offset of the Gray table (Q entries)
+    const TabEntry* tab;     // Gray table (Q entries, device memory)
     uint64_t unit_base;      // slot of this permanent's unit 0 in the partial arrays
     uint64_t units;          // number of units  (= groups * units_per_group)
     uint64_t units_per_group;
@@ -83,7 +86,6 @@ struct PrepItem {
 struct WalkArgs {
     const PermDesc* descs;
     const RowInfo* rowinfo;
-    const TabEntry* tab;
     const double* a;     // FP64 kept rows (interleaved complex)
     const double* a2;    // FP64 +-2a rows
     const float* af;     // FP32 copies

@@ -47,12 +47,12 @@ void gray_digits(uint64_t t, const uint32_t* radix, int nd, uint32_t* delta)
 
 namespace {
 
-double signed_weight(const std::vector<RowInfo>& rows, const std::vector<int>& digits, const uint32_t* delta)
+// prod_i (-1)^delta_i C(radix_i - 1, delta_i)
+double signed_weight(const std::vector<uint32_t>& radix, const uint32_t* delta)
 {
     double w = 1.0;
-    for (size_t i = 0; i < digits.size(); ++i) {
-        const RowInfo& x = rows[(size_t)digits[i]];
-        const double b = (double)binom_u64(x.mp, (int)delta[i]);
+    for (size_t i = 0; i < radix.size(); ++i) {
+        const double b = (double)binom_u64((int)radix[i] - 1, (int)delta[i]);
         w *= (delta[i] & 1u) ? -b : b;
     }
     return w;
@@ -95,8 +95,56 @@ std::vector<int> choose_lane_digits(const std::vector<int>& digits, const std::v
 
 }  // namespace
 
+int make_gray_table(const std::vector<uint32_t>& radix, std::vector<TabEntry>& out, std::string& err)
+{
+    const int nl = (int)radix.size();
+    uint64_t Q = 1;
+    for (uint32_t R : radix) {
+        if (R < 1) { err = "internal: radix 0"; return BBFG_ERANGE; }
+        Q *= R;
+        if (Q > (1u << 24)) { err = "internal: Gray table too long"; return BBFG_ERANGE; }
+    }
+    std::vector<uint32_t> cur((size_t)nl), prev((size_t)nl);
+    out.assign((size_t)Q, TabEntry{0u, 0u, 0.0});
+    for (uint32_t t = 0; t < (uint32_t)Q; ++t) {
+        gray_digits(t, radix.data(), nl, cur.data());
+        TabEntry e{0u, 0u, signed_weight(radix, cur.data())};
+        if (t > 0) {
+            int changed = -1, ndiff = 0, step = 0;
+            for (int i = 0; i < nl; ++i)
+                if (cur[(size_t)i] != prev[(size_t)i]) {
+                    ++ndiff;
+                    changed = i;
+                    step = (int)cur[(size_t)i] - (int)prev[(size_t)i];
+                }
+            if (ndiff != 1 || (step != 1 && step != -1)) { err = "internal: Gray step"; return BBFG_ERANGE; }
+            // Delta up by one: coefficient M' - 2 Delta drops by 2 -> add -2 a_i
+            e.row = (uint32_t)(2 * changed + (step > 0 ? 1 : 0));
+        }
+        out[t] = e;
+        prev = cur;
+    }
+    return BBFG_OK;
+}
+
+int TableCache::get(const std::vector<uint32_t>& radix, TablePtr* out, std::string& err)
+{
+    auto it = tables.find(radix);
+    if (it != tables.end()) {
+        *out = it->second;
+        return BBFG_OK;
+    }
+    auto t = std::make_shared<std::vector<TabEntry>>();
+    const int rc = make_gray_table(radix, *t, err);
+    if (rc) return rc;
+    entries += t->size();
+    tables.emplace(radix, t);
+    *out = t;
+    return BBFG_OK;
+}
+
 int build_plan(const int32_t* mult, int n_rows, int n_cols, uint64_t slots, const PlanParams& pp, HostPlan& P,
-               std::string& err)
+               std::string& err, TableCache* cache)
 {
     P = HostPlan();
     if (n_rows < 0) { err = "n_rows < 0"; return BBFG_EINVAL; }
@@ -193,37 +241,53 @@ int build_plan(const int32_t* mult, int n_rows, int n_cols, uint64_t slots, cons
     P.span = P.H * P.Q;
     if ((uint64_t)P.lane_product * P.span != P.n_addends) { err = "internal: digit split mismatch"; return BBFG_ERANGE; }
 
-    // Gray table of the low digits
-    const int nl = (int)P.low_digits.size();
-    std::vector<uint32_t> radix((size_t)nl), cur((size_t)nl), prev((size_t)nl);
-    for (int i = 0; i < nl; ++i) radix[(size_t)i] = P.rows[(size_t)P.low_digits[(size_t)i]].radix;
-    P.table.resize(P.Q);
-    for (uint32_t t = 0; t < P.Q; ++t) {
-        gray_digits(t, radix.data(), nl, cur.data());
-        TabEntry e{0u, 0u, signed_weight(P.rows, P.low_digits, cur.data())};
-        if (t > 0) {
-            int changed = -1, ndiff = 0, step = 0;
-            for (int i = 0; i < nl; ++i)
-                if (cur[(size_t)i] != prev[(size_t)i]) {
-                    ++ndiff;
-                    changed = i;
-                    step = (int)cur[(size_t)i] - (int)prev[(size_t)i];
-                }
-            if (ndiff != 1 || (step != 1 && step != -1)) { err = "internal: Gray step"; return BBFG_ERANGE; }
-            // Delta up by one: coefficient M' - 2 Delta drops by 2 -> add -2 a_k
-            const int k = P.low_digits[(size_t)changed];
-            e.row = (uint32_t)(2 * k + (step > 0 ? 1 : 0));
+    // renumber the kept rows: low digits first, so that a Gray table depends on
+    // the low radices only
+    {
+        std::vector<int> order(P.low_digits.begin(), P.low_digits.end());
+        std::vector<char> is_low((size_t)P.r, 0);
+        for (int k : P.low_digits) is_low[(size_t)k] = 1;
+        for (int k = 0; k < P.r; ++k)
+            if (!is_low[(size_t)k]) order.push_back(k);
+        std::vector<int> new_index((size_t)P.r);
+        for (int i = 0; i < P.r; ++i) new_index[(size_t)order[(size_t)i]] = i;
+        std::vector<int> src_row((size_t)P.r), mult_k((size_t)P.r);
+        std::vector<RowInfo> rows((size_t)P.r);
+        for (int i = 0; i < P.r; ++i) {
+            src_row[(size_t)i] = P.src_row[(size_t)order[(size_t)i]];
+            mult_k[(size_t)i] = P.mult[(size_t)order[(size_t)i]];
+            rows[(size_t)i] = P.rows[(size_t)order[(size_t)i]];
         }
-        P.table[t] = e;
-        prev = cur;
+        P.src_row.swap(src_row);
+        P.mult.swap(mult_k);
+        P.rows.swap(rows);
+        P.pivot = new_index[(size_t)P.pivot];
+        for (auto* v : {&P.lane_digits, &P.low_digits, &P.high_digits})
+            for (int& k : *v) k = new_index[(size_t)k];
     }
+
+    // Gray table of the low digits
+    P.low_radix.clear();
+    for (int k : P.low_digits) P.low_radix.push_back(P.rows[(size_t)k].radix);
+    if (cache) {
+        const int rc = cache->get(P.low_radix, &P.table, err);
+        if (rc) return rc;
+    } else {
+        auto t = std::make_shared<std::vector<TabEntry>>();
+        const int rc = make_gray_table(P.low_radix, *t, err);
+        if (rc) return rc;
+        P.table = t;
+    }
+    if (P.table->size() != P.Q) { err = "internal: table length"; return BBFG_ERANGE; }
 
     // work units: equal contiguous (block, position) ranges per lane group
     const uint64_t total = (uint64_t)P.groups * P.span;  // wavefront-steps
     const uint64_t S = slots > 0 ? slots : 1;
     uint64_t units;
-    if (total < S * pp.l_min) {
-        units = (total + pp.l_min - 1) / pp.l_min;
+    if (pp.l_batch > 0) {
+        units = (total + pp.l_batch - 1) / pp.l_batch;
+    } else if (total < S * pp.l_floor) {
+        units = (total + pp.l_floor - 1) / pp.l_floor;
     } else {
         const double k = std::max(1.0, std::nearbyint((double)total / ((double)S * (double)pp.l_target)));
         units = S * (uint64_t)k;

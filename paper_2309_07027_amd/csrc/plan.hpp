@@ -2,6 +2,8 @@
 #pragma once
 
 #include <cstdint>
+#include <map>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -12,11 +14,30 @@ namespace bbfg {
 struct PlanParams {
     uint32_t q_max = 4096;     // largest Gray block length (rows of multiplicity <= 3)
     uint32_t q_max_heavy = 512;  // largest Gray block length when some M'_k > 3
-    uint64_t l_min = 256;      // shortest unit (positions per lane) for small permanents
-    uint64_t l_target = 4096;  // preferred unit length for large permanents
+    // single launches: units fill every resident wavefront slot when the sum allows
+    uint64_t l_floor = 16;     // shortest unit (positions per lane) of a single launch
+    uint64_t l_target = 4096;  // unit length of sums larger than one round of slots
+    // batched launches: units of a fixed length, so an item's split depends on its
+    // own shape only (0 = use the single-launch rule)
+    uint64_t l_batch = 0;
+};
+
+using TablePtr = std::shared_ptr<const std::vector<TabEntry>>;
+
+// Gray table of low digits with radices `radix` (digit 0 fastest); entry rows
+// index the +-2a rows of kept row = digit index.
+int make_gray_table(const std::vector<uint32_t>& radix, std::vector<TabEntry>& out, std::string& err);
+
+// Tables shared between plans with the same low radices.
+struct TableCache {
+    std::map<std::vector<uint32_t>, TablePtr> tables;
+    size_t entries = 0;
+    int get(const std::vector<uint32_t>& radix, TablePtr* out, std::string& err);
 };
 
 // Decomposition of one permanent (see walk.hip for how the kernel uses it).
+// Kept rows are numbered low digits first (in low-digit order), then the other
+// rows in input order.
 struct HostPlan {
     int n = 0;                     // columns
     int r = 0;                     // kept rows (M_k > 0)
@@ -36,14 +57,16 @@ struct HostPlan {
     uint64_t units = 1;
     uint64_t n_addends = 1;        // C'
     double err_coeff = 1.0;
-    std::vector<TabEntry> table;   // Q entries
+    std::vector<uint32_t> low_radix;  // radices of the low digits (table key)
+    TablePtr table;                // Q entries
 };
 
 // Plans perm(A, M) for the n_rows multiplicities `mult` (sum == n_cols), for a
 // device with `slots` resident walk wavefronts.  Returns 0 or a bbfg_status and
 // sets `err`.
+// Tables come from `cache` when given, else are built for this plan.
 int build_plan(const int32_t* mult, int n_rows, int n_cols, uint64_t slots, const PlanParams& pp, HostPlan& out,
-               std::string& err);
+               std::string& err, TableCache* cache = nullptr);
 
 // Reflected mixed-radix Gray code (digit 0 fastest): Delta_k at position t.
 void gray_digits(uint64_t t, const uint32_t* radix, int nd, uint32_t* delta);

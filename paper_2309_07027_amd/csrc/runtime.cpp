@@ -3,8 +3,10 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
+#include <unordered_set>
 
 namespace bbfg {
 
@@ -15,7 +17,9 @@ namespace {
 thread_local std::string t_err = "no error";
 thread_local hipStream_t t_stream = nullptr;
 std::mutex g_ctx_mu;
-std::map<int, std::unique_ptr<Context>> g_ctx;
+// Contexts live until the process ends (never destroyed: freeing device memory
+// during static destruction could race the HIP runtime's own teardown).
+std::map<int, Context*> g_ctx;
 }  // namespace
 
 int set_error(int code, const char* fmt, ...)
@@ -114,7 +118,7 @@ int get_context(Context** out)
     std::lock_guard<std::mutex> lk(g_ctx_mu);
     auto it = g_ctx.find(dev);
     if (it != g_ctx.end()) {
-        *out = it->second.get();
+        *out = it->second;
         return BBFG_OK;
     }
     auto c = std::make_unique<Context>();
@@ -128,8 +132,15 @@ int get_context(Context** out)
     BBFG_HIP(hipEventCreate(&c->ev0));
     BBFG_HIP(hipEventCreate(&c->ev1));
     BBFG_TRY(c->counter.ensure(256));
+    if (const char* path = std::getenv("BBFG_AUTOTUNE_CACHE")) {
+        FILE* f = std::fopen(path, "r");
+        if (f) {
+            std::fclose(f);
+            (void)load_autotune_file(*c, path);
+        }
+    }
     *out = c.get();
-    g_ctx[dev] = std::move(c);
+    g_ctx[dev] = c.release();
     return BBFG_OK;
 }
 
@@ -169,12 +180,39 @@ int batch_waves(Context& c, int bucket, int f32, int* waves)
     return BBFG_OK;
 }
 
-int get_plan(Context& c, const int32_t* mult, int n_rows, int n_cols, int f32, std::shared_ptr<const HostPlan>* out)
+uint64_t batch_unit_length(Context& c, int n, int f32)
 {
+    auto it = c.batch_L.find(std::make_pair(n, f32));
+    return it == c.batch_L.end() ? kDefaultBatchUnit : it->second;
+}
+
+int load_autotune_file(Context& c, const char* path)
+{
+    FILE* f = std::fopen(path, "r");
+    if (!f) return set_error(BBFG_EINVAL, "cannot open autotune cache %s", path);
+    int prec = 0, n = 0;
+    unsigned long long L = 0;
+    int count = 0;
+    while (std::fscanf(f, "%d %d %llu", &prec, &n, &L) == 3) {
+        if (n >= 1 && n <= kMaxN && L >= 1 && (prec == 0 || prec == 1)) {
+            c.batch_L[std::make_pair(n, prec)] = (uint64_t)L;
+            ++count;
+        }
+    }
+    std::fclose(f);
+    return count > 0 ? BBFG_OK : set_error(BBFG_EINVAL, "no entries in autotune cache %s", path);
+}
+
+int get_plan(Context& c, const int32_t* mult, int n_rows, int n_cols, int f32, int mode,
+             std::shared_ptr<const HostPlan>* out)
+{
+    PlanParams pp = c.params;
+    if (mode == PLAN_BATCH) pp.l_batch = batch_unit_length(c, n_cols, f32);
     std::string key;
-    key.reserve(16 + 4 * (size_t)n_rows);
+    key.reserve(32 + 4 * (size_t)n_rows);
     key.append(reinterpret_cast<const char*>(&n_cols), sizeof n_cols);
     key.push_back((char)f32);
+    key.append(reinterpret_cast<const char*>(&pp.l_batch), sizeof pp.l_batch);
     key.append(reinterpret_cast<const char*>(mult), sizeof(int32_t) * (size_t)n_rows);
     auto it = c.plans.find(key);
     if (it != c.plans.end()) {
@@ -183,13 +221,60 @@ int get_plan(Context& c, const int32_t* mult, int n_rows, int n_cols, int f32, s
     }
     uint64_t slots = 1;
     if (n_cols >= 1) BBFG_TRY(walk_slots(c, n_cols, f32, &slots));
+    if (c.tables.entries > kTableEntryCap || c.plans.size() > kPlanCap) BBFG_TRY(flush_plans(c));
     auto p = std::make_shared<HostPlan>();
     std::string err;
-    const int rc = build_plan(mult, n_rows, n_cols, slots, c.params, *p, err);
+    const int rc = build_plan(mult, n_rows, n_cols, slots, pp, *p, err, &c.tables);
     if (rc != BBFG_OK) return set_error(rc, "%s", err.c_str());
-    if (c.plans.size() > 8192) c.plans.clear();
     c.plans.emplace(key, p);
     *out = p;
+    return BBFG_OK;
+}
+
+int device_table(Context& c, const HostPlan& p, const TabEntry** out)
+{
+    const void* host = p.table.get();
+    auto it = c.dev_tables.find(host);
+    if (it != c.dev_tables.end()) {
+        *out = it->second;
+        return BBFG_OK;
+    }
+    const size_t bytes = sizeof(TabEntry) * p.table->size();
+    const size_t need = (bytes + 255) / 256 * 256;
+    if (c.tab_chunk < c.tab_chunks.size() && c.tab_used + need > c.tab_chunks[c.tab_chunk]->cap) {
+        ++c.tab_chunk;
+        c.tab_used = 0;
+    }
+    if (c.tab_chunk == c.tab_chunks.size()) {
+        auto b = std::make_unique<DevBuf>();
+        BBFG_TRY(b->ensure(std::max<size_t>(need, kTableChunkBytes)));
+        c.tab_chunks.push_back(std::move(b));
+        c.tab_used = 0;
+    }
+    TabEntry* dst = reinterpret_cast<TabEntry*>(c.tab_chunks[c.tab_chunk]->as<char>() + c.tab_used);
+    // synchronous: once listed, a table is complete for work on any stream
+    hipStream_t s = current_stream();
+    BBFG_HIP(hipMemcpyAsync(dst, p.table->data(), bytes, hipMemcpyHostToDevice, s));
+    BBFG_HIP(hipStreamSynchronize(s));
+    c.tab_used += need;
+    c.dev_tables.emplace(host, dst);
+    *out = dst;
+    return BBFG_OK;
+}
+
+int flush_plans(Context& c)
+{
+    // device tables are about to be reused: nothing may still read them
+    BBFG_HIP(hipDeviceSynchronize());
+    for (auto& kv : c.graphs) (void)hipGraphExecDestroy(kv.second);
+    c.graphs.clear();
+    c.graph_seen.clear();
+    c.dev_tables.clear();
+    c.tab_chunk = 0;
+    c.tab_used = 0;
+    c.tables.tables.clear();
+    c.tables.entries = 0;
+    c.plans.clear();
     return BBFG_OK;
 }
 
@@ -197,26 +282,26 @@ int get_plan(Context& c, const int32_t* mult, int n_rows, int n_cols, int f32, s
 // the permanent engine
 // ---------------------------------------------------------------------------
 int run_perms(Context& c, std::vector<PermItem>& items, int f32, bool single, double* out_host, double* diag_host,
-              RunResult* rr, bool sync)
+              RunResult* rr, bool sync, bool use_graph)
 {
     const size_t nitem = items.size();
     if (nitem == 0) return BBFG_OK;
     if (single && nitem != 1) return set_error(BBFG_EINVAL, "internal: single launch with %zu items", nitem);
     hipStream_t s = current_stream();
 
-    // distinct plans (tables and row records are shared between equal shapes)
-    std::unordered_map<const HostPlan*, std::pair<size_t, size_t>> plan_slot;  // -> (rowinfo off, tab off)
-    std::vector<const HostPlan*> uniq;
-    size_t n_rowinfo = 0, n_tab = 0, n_srcrow = 0, n_srccol = 0;
+    // distinct plans (row records are shared between equal shapes; Gray tables
+    // are resident on the device and shared between equal low radices)
+    std::unordered_map<const HostPlan*, std::pair<size_t, const TabEntry*>> plan_slot;  // -> (rowinfo off, table)
+    size_t n_rowinfo = 0, n_srcrow = 0, n_srccol = 0;
     uint64_t a_elems = 0;
     int nmax = 0;
     for (auto& it : items) {
         const HostPlan* p = it.plan.get();
         if (plan_slot.find(p) == plan_slot.end()) {
-            plan_slot[p] = {n_rowinfo, n_tab};
+            const TabEntry* dt = nullptr;
+            BBFG_TRY(device_table(c, *p, &dt));
+            plan_slot[p] = {n_rowinfo, dt};
             n_rowinfo += (size_t)p->r;
-            n_tab += p->table.size();
-            uniq.push_back(p);
         }
         n_srcrow += (size_t)p->r;
         if (it.col_map) n_srccol += (size_t)p->n;
@@ -246,7 +331,6 @@ int run_perms(Context& c, std::vector<PermItem>& items, int f32, bool single, do
     Layout L;
     const size_t off_desc = L.add(sizeof(PermDesc) * nitem);
     const size_t off_row = L.add(sizeof(RowInfo) * std::max<size_t>(1, n_rowinfo));
-    const size_t off_tab = L.add(sizeof(TabEntry) * std::max<size_t>(1, n_tab));
     const size_t off_prep = L.add(sizeof(PrepItem) * nitem);
     const size_t off_src = L.add(sizeof(uint32_t) * std::max<size_t>(1, n_srcrow));
     const size_t off_col = L.add(sizeof(uint32_t) * std::max<size_t>(1, n_srccol));
@@ -256,15 +340,11 @@ int run_perms(Context& c, std::vector<PermItem>& items, int f32, bool single, do
     char* H = c.hmeta.as<char>();
     PermDesc* hd = reinterpret_cast<PermDesc*>(H + off_desc);
     RowInfo* hr = reinterpret_cast<RowInfo*>(H + off_row);
-    TabEntry* ht = reinterpret_cast<TabEntry*>(H + off_tab);
     PrepItem* hp = reinterpret_cast<PrepItem*>(H + off_prep);
     uint32_t* hs = reinterpret_cast<uint32_t*>(H + off_src);
     uint32_t* hc = reinterpret_cast<uint32_t*>(H + off_col);
-    for (const HostPlan* p : uniq) {
-        const auto sl = plan_slot[p];
-        std::memcpy(hr + sl.first, p->rows.data(), sizeof(RowInfo) * (size_t)p->r);
-        std::memcpy(ht + sl.second, p->table.data(), sizeof(TabEntry) * p->table.size());
-    }
+    for (const auto& kv : plan_slot)
+        std::memcpy(hr + kv.second.first, kv.first->rows.data(), sizeof(RowInfo) * (size_t)kv.first->r);
     uint64_t a_cursor = 0;
     size_t s_cursor = 0, c_cursor = 0;
     for (size_t i = 0; i < nitem; ++i) {
@@ -275,7 +355,7 @@ int run_perms(Context& c, std::vector<PermItem>& items, int f32, bool single, do
         d.a_off = a_cursor;
         d.a2_off = a_cursor + (uint64_t)p.r * p.n;
         a_cursor += (uint64_t)p.r * p.n * 3u;
-        d.tab_off = sl.second;
+        d.tab = sl.second;
         d.unit_base = unit_base[i];
         d.units = p.units;
         d.units_per_group = p.units_per_group;
@@ -322,13 +402,11 @@ int run_perms(Context& c, std::vector<PermItem>& items, int f32, bool single, do
     BBFG_TRY(c.results.ensure(sizeof(double) * 4 * nitem));
     BBFG_TRY(c.hres.ensure(sizeof(double) * 4 * nitem));
     char* D = c.meta.as<char>();
-    BBFG_HIP(hipMemcpyAsync(D, H, L.size, hipMemcpyHostToDevice, s));
 
     WalkArgs W;
     std::memset(&W, 0, sizeof W);
     W.descs = reinterpret_cast<const PermDesc*>(D + off_desc);
     W.rowinfo = reinterpret_cast<const RowInfo*>(D + off_row);
-    W.tab = reinterpret_cast<const TabEntry*>(D + off_tab);
     W.a = c.arena_d.as<double>();
     W.a2 = c.arena_d.as<double>();
     W.af = c.arena_f.as<float>();
@@ -339,31 +417,89 @@ int run_perms(Context& c, std::vector<PermItem>& items, int f32, bool single, do
     W.counter = c.counter.as<uint32_t>();
     W.total_units = (uint32_t)total_units;
 
-    BBFG_HIP(launch_prep((uint32_t)nitem, s, reinterpret_cast<const PrepItem*>(D + off_prep),
-                         reinterpret_cast<const uint32_t*>(D + off_src), reinterpret_cast<const uint32_t*>(D + off_col),
-                         c.arena_d.as<double>(),
-                         c.arena_d.as<double>(), c.arena_f.as<float>(), c.arena_f.as<float>()));
-    if (single) {
-        BBFG_HIP(hipEventRecord(c.ev0, s));
-        BBFG_HIP(launch_walk_single(items[0].plan->n, f32, (uint32_t)total_units, s, W, 0u));
-        BBFG_HIP(hipEventRecord(c.ev1, s));
-    } else {
-        const int bucket = batch_bucket_max(nmax, f32);
+    int bucket = 0;
+    uint64_t grid = total_units;
+    if (!single) {
+        bucket = batch_bucket_max(nmax, f32);
         if (bucket < 0) return set_error(BBFG_ERANGE, "no batch kernel for n=%d", nmax);
         int waves = 1;
         BBFG_TRY(batch_waves(c, bucket, f32, &waves));
-        const uint64_t grid = std::min<uint64_t>((uint64_t)waves * (uint64_t)c.n_cu, total_units);
-        BBFG_HIP(launch_reset_counter(W.counter, s));
-        BBFG_HIP(hipEventRecord(c.ev0, s));
-        BBFG_HIP(launch_walk_batch(bucket, f32, (uint32_t)grid, s, W));
-        BBFG_HIP(hipEventRecord(c.ev1, s));
+        grid = std::min<uint64_t>((uint64_t)waves * (uint64_t)c.n_cu, total_units);
     }
     double* R = c.results.as<double>();
-    BBFG_HIP(launch_finalize((uint32_t)nitem, s, W.descs, W.partials, R, R + 2 * nitem));
+    double* HR = c.hres.as<double>();
+
+    // Everything one evaluation puts on a stream (also what a graph captures):
+    // metadata upload, gather, walk, finalize and, when results go back to the
+    // host, their download.  No memset: the unit counter is cleared by a kernel.
+    auto enqueue = [&](hipStream_t q, bool timed) -> int {
+        BBFG_HIP(hipMemcpyAsync(D, H, L.size, hipMemcpyHostToDevice, q));
+        BBFG_HIP(launch_prep((uint32_t)nitem, q, reinterpret_cast<const PrepItem*>(D + off_prep),
+                             reinterpret_cast<const uint32_t*>(D + off_src),
+                             reinterpret_cast<const uint32_t*>(D + off_col), c.arena_d.as<double>(),
+                             c.arena_d.as<double>(), c.arena_f.as<float>(), c.arena_f.as<float>()));
+        if (!single) BBFG_HIP(launch_reset_counter(W.counter, q));
+        if (timed) BBFG_HIP(hipEventRecord(c.ev0, q));
+        if (single) BBFG_HIP(launch_walk_single(items[0].plan->n, f32, (uint32_t)total_units, q, W, 0u));
+        else BBFG_HIP(launch_walk_batch(bucket, f32, (uint32_t)grid, q, W));
+        if (timed) BBFG_HIP(hipEventRecord(c.ev1, q));
+        BBFG_HIP(launch_finalize((uint32_t)nitem, q, W.descs, W.partials, R, R + 2 * nitem));
+        if (sync) BBFG_HIP(hipMemcpyAsync(HR, R, sizeof(double) * 4 * nitem, hipMemcpyDeviceToHost, q));
+        return BBFG_OK;
+    };
+
+    bool launched = false;
+    if (use_graph && sync) {
+        // A launch sequence seen before is captured once and replayed.  The
+        // captured nodes hold sizes and addresses only (every kernel reads its
+        // shapes from the uploaded metadata), so the key is the layout of the
+        // metadata image, the launch shapes and every buffer address; the image
+        // itself is copied again by each replay.
+        uint64_t key = 1469598103934665603ull;
+        auto mix = [&key](const void* p, size_t n) {
+            const unsigned char* b = static_cast<const unsigned char*>(p);
+            for (size_t i = 0; i < n; ++i) key = (key ^ b[i]) * 1099511628211ull;
+        };
+        mix(&W, sizeof W);
+        const uint64_t extra[] = {nitem, (uint64_t)single, (uint64_t)f32, (uint64_t)bucket, grid, L.size, off_desc, off_row, off_prep,
+                                  off_src, off_col, off_uitem, (uint64_t)(uintptr_t)H, (uint64_t)(uintptr_t)D,
+                                  (uint64_t)(uintptr_t)R, (uint64_t)(uintptr_t)HR, (uint64_t)(uintptr_t)c.arena_d.p,
+                                  (uint64_t)(uintptr_t)c.arena_f.p};
+        mix(extra, sizeof extra);
+        auto git = c.graphs.find(key);
+        if (git == c.graphs.end() && c.graph_seen.count(key)) {
+            if (!c.cstream) BBFG_HIP(hipStreamCreateWithFlags(&c.cstream, hipStreamNonBlocking));
+            hipGraph_t g = nullptr;
+            BBFG_HIP(hipStreamBeginCapture(c.cstream, hipStreamCaptureModeThreadLocal));
+            const int rc = enqueue(c.cstream, false);
+            hipGraph_t gcap = nullptr;
+            const hipError_t ec = hipStreamEndCapture(c.cstream, &gcap);
+            if (rc != BBFG_OK) return rc;
+            if (ec != hipSuccess) return set_error(BBFG_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(ec));
+            g = gcap;
+            hipGraphExec_t exec = nullptr;
+            BBFG_HIP(hipGraphInstantiate(&exec, g, nullptr, nullptr, 0));
+            (void)hipGraphDestroy(g);
+            if (c.graphs.size() >= 64) {
+                for (auto& kv : c.graphs) (void)hipGraphExecDestroy(kv.second);
+                c.graphs.clear();
+            }
+            git = c.graphs.emplace(key, exec).first;
+        }
+        if (git != c.graphs.end()) {
+            BBFG_HIP(hipEventRecord(c.ev0, s));
+            BBFG_HIP(hipGraphLaunch(git->second, s));
+            BBFG_HIP(hipEventRecord(c.ev1, s));
+            launched = true;
+            if (rr) rr->graph = true;
+        } else {
+            if (c.graph_seen.size() > 4096) c.graph_seen.clear();
+            c.graph_seen.insert(key);
+        }
+    }
+    if (!launched) BBFG_TRY(enqueue(s, true));
     if (rr) rr->units = total_units;
     if (!sync) return BBFG_OK;
-    double* HR = c.hres.as<double>();
-    BBFG_HIP(hipMemcpyAsync(HR, R, sizeof(double) * 4 * nitem, hipMemcpyDeviceToHost, s));
     BBFG_HIP(hipStreamSynchronize(s));
     if (out_host) std::memcpy(out_host, HR, sizeof(double) * 2 * nitem);
     if (diag_host) std::memcpy(diag_host, HR + 2 * nitem, sizeof(double) * 2 * nitem);

@@ -10,6 +10,7 @@
 #include <mutex>
 #include <string>
 #include <unordered_map>
+#include <unordered_set>
 #include <vector>
 
 #include "../../include/bbfg.h"
@@ -39,6 +40,10 @@ const char* last_error();
 struct DevBuf {
     void* p = nullptr;
     size_t cap = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { release(); }
     int ensure(size_t bytes);
     void release();
     template <typename T>
@@ -78,8 +83,27 @@ struct Context {
     std::map<std::pair<int, int>, int> occ_single;  // (n, f32) -> waves per CU
     std::map<std::pair<int, int>, int> occ_batch;   // (bucket, f32) -> waves per CU
     std::unordered_map<std::string, std::shared_ptr<const HostPlan>> plans;
+    // Gray tables shared between plans (host), and their device copies:
+    // bump-allocated in chunks that are never moved while referenced
+    TableCache tables;
+    std::vector<std::unique_ptr<DevBuf>> tab_chunks;
+    size_t tab_chunk = 0, tab_used = 0;  // current chunk, bytes used in it
+    std::unordered_map<const void*, const TabEntry*> dev_tables;
     PlanParams params;
+    std::map<std::pair<int, int>, uint64_t> batch_L;  // (n, f32) -> tuned unit length
+    // captured batch evaluations, keyed by layout (replayed on repeats)
+    std::unordered_map<uint64_t, hipGraphExec_t> graphs;
+    std::unordered_set<uint64_t> graph_seen;
+    hipStream_t cstream = nullptr;  // capture stream
 };
+
+// Unit length used for n-column permanents in batched launches.
+constexpr uint64_t kDefaultBatchUnit = 512;
+uint64_t batch_unit_length(Context& c, int n, int f32);
+
+// Plans for a single launch (units fill the device) or for batched launches
+// (fixed unit length: the split depends on the item's shape only).
+enum PlanMode { PLAN_SINGLE = 0, PLAN_BATCH = 1 };
 
 // Context of the current HIP device (created on first use).
 int get_context(Context** out);
@@ -88,7 +112,18 @@ void set_current_stream(hipStream_t s);
 
 int walk_slots(Context& c, int n, int f32, uint64_t* slots);
 int batch_waves(Context& c, int bucket, int f32, int* waves);
-int get_plan(Context& c, const int32_t* mult, int n_rows, int n_cols, int f32, std::shared_ptr<const HostPlan>* out);
+int get_plan(Context& c, const int32_t* mult, int n_rows, int n_cols, int f32, int mode,
+             std::shared_ptr<const HostPlan>* out);
+// Device copy of a plan's Gray table (uploaded on first use, then resident).
+int device_table(Context& c, const HostPlan& p, const TabEntry** out);
+// Caches are bounded: past these sizes plans, tables and captured graphs are
+// dropped (after the device has drained) and rebuilt on demand.
+constexpr size_t kPlanCap = 16384;
+constexpr size_t kTableEntryCap = size_t(4) << 20;  // 64 MiB of table entries
+constexpr size_t kTableChunkBytes = size_t(8) << 20;
+int flush_plans(Context& c);
+// Loads "precision n L" lines written by bbfg_autotune.
+int load_autotune_file(Context& c, const char* path);
 
 // Is p device memory (of any device)?
 bool is_device_ptr(const void* p);
@@ -110,8 +145,9 @@ struct PermItem {
 };
 
 struct RunResult {
-    double kernel_ms = 0.0;
+    double kernel_ms = 0.0;  // walk kernel (eager) or whole graph (replay)
     uint64_t units = 0;
+    bool graph = false;      // evaluated by replaying a captured graph
 };
 
 // Evaluates items (all n >= 1).  The (re, im) results stay in c.results (item
@@ -119,7 +155,9 @@ struct RunResult {
 // diagnostics (err_est, kappa) to diag_host[2*i].  With sync = false nothing is
 // copied back and the stream is not synchronised (the caller queues more work
 // that reads c.results).  single = true uses the one-permanent launch.
+// use_graph = true captures a layout into a hipGraph the second time it is
+// seen and replays the graph from then on.
 int run_perms(Context& c, std::vector<PermItem>& items, int f32, bool single, double* out_host, double* diag_host,
-              RunResult* rr, bool sync = true);
+              RunResult* rr, bool sync = true, bool use_graph = false);
 
 }  // namespace bbfg

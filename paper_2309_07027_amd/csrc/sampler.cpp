@@ -159,7 +159,7 @@ int cc_step(Context& c, std::vector<ActiveSample>& act, double* kernel_ms, uint6
                 mult.push_back(kv.second);
             }
             std::shared_ptr<const HostPlan> plan;
-            BBFG_TRY(get_plan(c, mult.data(), (int)mult.size(), k - 1, 0, &plan));
+            BBFG_TRY(get_plan(c, mult.data(), (int)mult.size(), k - 1, 0, PLAN_BATCH, &plan));
             st.minor_off = (uint32_t)items.size();
             for (int l = 0; l < k; ++l) {
                 keep.emplace_back();

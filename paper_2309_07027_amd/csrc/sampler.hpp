@@ -35,7 +35,6 @@ struct CCJob {
     std::vector<int32_t> out;   // n_samples x m
     double kernel_ms = 0.0;
     uint64_t n_addends = 0;
-    ~CCJob() { A.release(); }
 };
 
 struct ActiveSample {

@@ -197,7 +197,7 @@ BBFG_FN void walk_unit(const WalkArgs& A, const PermDesc& d, uint32_t u_local, u
     const bool valid = lane_idx < d.lane_product;
     if (!valid) lane_idx = 0;
 
-    kptr<TabEntry> tab = kconst(A.tab + d.tab_off);
+    kptr<TabEntry> tab = kconst(d.tab);
     kptr<Real> a2 = kconst(RowsOf<Real>::a2(A) + 2 * d.a2_off);
     const uint32_t Q = d.Q;
 

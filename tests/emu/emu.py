@@ -23,11 +23,13 @@ def build():
     return EXE
 
 
-def run(A, M, slots: int, f32: bool = False):
-    """Emulated perm_bbfg: (value, rel_err_est, kappa, units)."""
+def run(A, M, slots: int, f32: bool = False, l_batch: int = 0):
+    """Emulated evaluation: (value, rel_err_est, kappa, units).  l_batch = 0 plans
+    the permanent as perm_bbfg does; l_batch > 0 as a batched launch with that
+    unit length."""
     A = np.ascontiguousarray(np.asarray(A, dtype=np.complex128))
     r, n = A.shape
-    lines = [f"{r} {n} {int(slots)} {1 if f32 else 0}", " ".join(str(int(m)) for m in M)]
+    lines = [f"{r} {n} {int(slots)} {1 if f32 else 0} {int(l_batch)}", " ".join(str(int(m)) for m in M)]
     lines.append(" ".join(f"{float(x.real).hex()} {float(x.imag).hex()}" for x in A.ravel()))
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0")
     p = subprocess.run([str(EXE)], input="\n".join(lines) + "\n", capture_output=True, text=True, env=env,

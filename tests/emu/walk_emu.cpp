@@ -8,8 +8,9 @@
 // every floating-point operation is written out (no contraction), the result
 // is expected to match the GPU bit for bit.
 //
-// stdin : n_rows n slots f32 / n_rows multiplicities / n_rows*n complex entries
-//         (re im, hex floats), row-major
+// stdin : n_rows n slots f32 l_batch / n_rows multiplicities / n_rows*n complex
+//         entries (re im, hex floats), row-major.  l_batch > 0 plans the item as a
+//         batched launch does (fixed unit length), 0 as a single launch.
 // stdout: re im rel_err_est kappa units   (hex floats, then an integer)
 #include <cmath>
 #include <cstdio>
@@ -33,9 +34,10 @@ void run_unit(const WalkArgs& W, const PermDesc& d, uint32_t u, uint32_t lane, d
     }
 }
 
-int read_case(int& n_rows, int& n, long long& slots, int& f32, std::vector<int32_t>& M, std::vector<double>& A)
+int read_case(int& n_rows, int& n, long long& slots, int& f32, long long& l_batch, std::vector<int32_t>& M,
+              std::vector<double>& A)
 {
-    if (std::scanf("%d %d %lld %d", &n_rows, &n, &slots, &f32) != 4) return 1;
+    if (std::scanf("%d %d %lld %d %lld", &n_rows, &n, &slots, &f32, &l_batch) != 5) return 1;
     M.resize((size_t)n_rows);
     for (int i = 0; i < n_rows; ++i)
         if (std::scanf("%d", &M[(size_t)i]) != 1) return 1;
@@ -46,12 +48,15 @@ int read_case(int& n_rows, int& n, long long& slots, int& f32, std::vector<int32
 }
 
 template <typename Real>
-int emulate(int n_rows, int n, long long slots, const std::vector<int32_t>& M, const std::vector<double>& A)
+int emulate(int n_rows, int n, long long slots, long long l_batch, const std::vector<int32_t>& M,
+            const std::vector<double>& A)
 {
     const int f32 = sizeof(Real) == 4 ? 1 : 0;
     HostPlan P;
     std::string err;
-    int rc = build_plan(M.data(), n_rows, n, (uint64_t)slots, PlanParams(), P, err);
+    PlanParams pp;
+    pp.l_batch = (uint64_t)l_batch;
+    int rc = build_plan(M.data(), n_rows, n, (uint64_t)slots, pp, P, err);
     if (rc) {
         std::fprintf(stderr, "plan error %d: %s\n", rc, err.c_str());
         return 2;
@@ -91,7 +96,7 @@ int emulate(int n_rows, int n, long long slots, const std::vector<int32_t>& M, c
     std::memset(&d, 0, sizeof d);
     d.a_off = 0;
     d.a2_off = (uint64_t)r * n;
-    d.tab_off = 0;
+    d.tab = P.table->data();
     d.unit_base = 0;
     d.units = P.units;
     d.units_per_group = P.units_per_group;
@@ -108,7 +113,6 @@ int emulate(int n_rows, int n, long long slots, const std::vector<int32_t>& M, c
     WalkArgs W;
     std::memset(&W, 0, sizeof W);
     W.rowinfo = P.rows.data();
-    W.tab = P.table.data();
     W.binom = binom.data();
     if (f32) {
         W.af = reinterpret_cast<const float*>(arena.data());
@@ -119,7 +123,7 @@ int emulate(int n_rows, int n, long long slots, const std::vector<int32_t>& M, c
     }
     emu_clear();
     emu_register(P.rows.data(), sizeof(RowInfo) * P.rows.size());
-    emu_register(P.table.data(), sizeof(TabEntry) * P.table.size());
+    emu_register(P.table->data(), sizeof(TabEntry) * P.table->size());
     emu_register(binom.data(), sizeof(double) * binom.size());
     emu_register(arena.data(), sizeof(Real) * arena.size());
 
@@ -198,12 +202,12 @@ int emulate(int n_rows, int n, long long slots, const std::vector<int32_t>& M, c
 int main()
 {
     int n_rows = 0, n = 0, f32 = 0;
-    long long slots = 0;
+    long long slots = 0, l_batch = 0;
     std::vector<int32_t> M;
     std::vector<double> A;
-    if (read_case(n_rows, n, slots, f32, M, A)) {
+    if (read_case(n_rows, n, slots, f32, l_batch, M, A)) {
         std::fprintf(stderr, "bad input\n");
         return 2;
     }
-    return f32 ? emulate<float>(n_rows, n, slots, M, A) : emulate<double>(n_rows, n, slots, M, A);
+    return f32 ? emulate<float>(n_rows, n, slots, l_batch, M, A) : emulate<double>(n_rows, n, slots, l_batch, M, A);
 }

@@ -46,9 +46,13 @@ def test_random_instances(oracle, kind):
             A, M = I.random_instance(rng, n, m=max(2, n // 2))
         else:
             A, M = I.random_instance(rng, n)
+        ref = oracle.perm_generalized(A, M)
         for slots in (1, 512):
             v, err, kappa, units = emu.run(A, M, slots)
-            assert rel(v, oracle.perm_generalized(A, M)) <= TOL, (n, M, slots)
+            assert rel(v, ref) <= TOL, (n, M, slots)
+        for L in (64, 512):
+            v, err, kappa, units = emu.run(A, M, 1, l_batch=L)
+            assert rel(v, ref) <= TOL, (n, M, L)
 
 
 def test_edge_shapes(oracle):
