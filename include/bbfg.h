@@ -149,8 +149,29 @@ int perm_batch(int32_t batch, const bbfg_c128 *A_packed, const int64_t *A_offset
                const int32_t *n_rows, const int32_t *row_mult_packed, const int64_t *row_mult_offset,
                const int32_t *n_cols, int32_t precision, bbfg_c128 *out, double *rel_err_est);
 
-/* Device time (ms) of the last perm_batch on this thread: the walk kernel when
- * launched directly, the whole replayed graph otherwise. */
+/*
+ * perm_minors -- every leave-one-column-out permanent of one matrix, from one
+ * joint walk: the minors of the Laplace expansion that the Clifford & Clifford
+ * step of Sec. 4 needs for all candidate output modes at once.  All minors
+ * share the rows, so one walk over the Delta box of Eq. bbfgrepeated (rows
+ * with multiplicities) forms the n_cols column sums once per addend and every
+ * product that leaves one column out (prefix and suffix products).
+ *
+ *   A         n_rows x n_cols complex, row-major, host or device.
+ *   row_mult  n_rows int32 multiplicities (host), sum = n_cols - 1.
+ *   n_cols    1 <= n_cols <= BBFG_MAX_N.
+ *   out       n_cols bbfg_c128, host or device:
+ *             out[l] = perm(A without column l, row_mult).
+ *
+ * FP64 with double-double reduction; no error estimate is formed (the
+ * magnitude sums are not accumulated).  n_cols = 1 gives the empty permanent 1.
+ * Errors: EINVAL (NULL pointer, negative multiplicity, sum != n_cols - 1),
+ * ERANGE (n_cols > BBFG_MAX_N), ENOMEM/EDEVICE.
+ */
+int perm_minors(const bbfg_c128 *A, int32_t n_rows, const int32_t *row_mult, int32_t n_cols, bbfg_c128 *out);
+
+/* Device time (ms) of the last perm_batch or perm_minors on this thread: the
+ * walk kernel when launched directly, the whole replayed graph otherwise. */
 double perm_batch_last_kernel_ms(void);
 
 /* 1 when the last perm_batch on this thread replayed a captured hipGraph.  A

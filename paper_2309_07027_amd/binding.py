@@ -76,6 +76,7 @@ SIGNATURES = {
     "bbfg_set_stream": (ctypes.c_int, [_P]),
     "perm_bbfg": (ctypes.c_int, [_P, _I32, _PI32, _I32, _P, ctypes.POINTER(Info)]),
     "perm_batch": (ctypes.c_int, [_I32, _P, _PI64, _PI32, _PI32, _PI64, _PI32, _I32, _P, _PD]),
+    "perm_minors": (ctypes.c_int, [_P, _I32, _PI32, _I32, _P]),
     "perm_batch_last_kernel_ms": (ctypes.c_double, []),
     "perm_batch_last_was_graph": (ctypes.c_int, []),
     "bs_sample": (ctypes.c_int, [_P, _I32, _PI32, _I32, ctypes.c_double, ctypes.c_uint64, _PI32,
@@ -225,6 +226,17 @@ def perm_batch_packed(A_packed, a_off, n_rows, M_packed, m_off, n_cols, precisio
 def perm_batch(mats, precision: int = BBFG_FP64, with_err: bool = False):
     """Permanents of [(A, M), ...] (host matrices) in one batched launch."""
     return perm_batch_packed(*pack_batch(mats), precision=precision, with_err=with_err)
+
+
+def perm_minors(A, M):
+    """[perm(A without column l, M) for l in range(n_cols)] (host numpy complex128);
+    sum(M) == n_cols - 1.  A may be a torch cuda tensor."""
+    ptr, keep, shape = _cmat_ptr(A)
+    m, pm = _i32(M)
+    out = np.zeros(shape[1], dtype=np.complex128)
+    _check(lib().perm_minors(ptr, shape[0], pm, shape[1], ctypes.c_void_p(out.ctypes.data)))
+    del keep
+    return out
 
 
 def batch_last_kernel_ms() -> float:

@@ -5,6 +5,7 @@
 #include <vector>
 
 #include "runtime.hpp"
+#include "sampler.hpp"
 
 using namespace bbfg;
 
@@ -188,6 +189,50 @@ int perm_batch(int32_t batch, const bbfg_c128* A_packed, const int64_t* A_offset
     if (rel_err_est)
         for (int32_t b = 0; b < batch; ++b) rel_err_est[b] = diag[2 * (size_t)b];
     return write_results(out, res.data(), (size_t)batch);
+}
+
+int perm_minors(const bbfg_c128* A, int32_t n_rows, const int32_t* row_mult, int32_t n_cols, bbfg_c128* out)
+{
+    if (!out) return set_error(BBFG_EINVAL, "out is NULL");
+    if (n_cols < 1) return set_error(BBFG_EINVAL, "n_cols = %d < 1", n_cols);
+    if (n_cols > kMaxN) return set_error(BBFG_ERANGE, "n_cols = %d exceeds the maximum %d", n_cols, kMaxN);
+    BBFG_TRY(validate_shape(row_mult, n_rows, n_cols - 1, kMaxN - 1));
+    if (!A) return set_error(BBFG_EINVAL, "A is NULL");
+    std::vector<double> res(2 * (size_t)n_cols, 0.0);
+    if (n_cols == 1) {
+        res[0] = 1.0;  // the empty permanent
+        return write_results(out, res.data(), 1);
+    }
+    Context* c = nullptr;
+    BBFG_TRY(get_context(&c));
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    const double* Ad = nullptr;
+    BBFG_TRY(device_view(*c, A, (uint64_t)n_rows * (uint64_t)n_cols, &Ad));
+    PermItem proto;
+    proto.src = Ad;
+    proto.src_off = 0;
+    proto.ld = (uint32_t)n_cols;
+    proto.n_rows = n_rows;
+    proto.n = n_cols - 1;
+    proto.mult = row_mult;
+    BBFG_TRY(get_plan(*c, row_mult, n_rows, n_cols - 1, 0, PLAN_BATCH, &proto.plan));
+    std::vector<int32_t> cols((size_t)n_cols);
+    for (int32_t j = 0; j < n_cols; ++j) cols[(size_t)j] = j;
+    std::deque<std::vector<int32_t>> keep;
+    std::vector<PermItem> items;
+    std::vector<uint32_t> slot((size_t)n_cols);
+    add_minor_items(proto, cols.data(), keep, items, 0, slot.data());
+    size_t nres = 0;
+    for (auto& it : items) nres += (size_t)it.targets;
+    std::vector<double> r2(2 * nres);
+    RunResult rr;
+    BBFG_TRY(run_perms(*c, items, 0, false, r2.data(), nullptr, &rr));
+    t_batch_kernel_ms = rr.kernel_ms;
+    for (int32_t l = 0; l < n_cols; ++l) {
+        res[2 * (size_t)l] = r2[2 * (size_t)slot[(size_t)l]];
+        res[2 * (size_t)l + 1] = r2[2 * (size_t)slot[(size_t)l] + 1];
+    }
+    return write_results(out, res.data(), (size_t)n_cols);
 }
 
 double perm_batch_last_kernel_ms(void) { return t_batch_kernel_ms; }

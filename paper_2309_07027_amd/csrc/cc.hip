@@ -38,6 +38,7 @@ constexpr int kCCThreads = 256;
 
 __global__ __launch_bounds__(kCCThreads) void cc_weights_kernel(const CCStep* __restrict__ steps,
                                                                 const int32_t* __restrict__ pi,
+                                                                const uint32_t* __restrict__ slot,
                                                                 const double* __restrict__ minors,
                                                                 int32_t* __restrict__ drawn, double* __restrict__ wsum)
 {
@@ -53,8 +54,9 @@ __global__ __launch_bounds__(kCCThreads) void cc_weights_kernel(const CCStep* __
         } else {
             for (int l = 0; l < st.k; ++l) {
                 const double ar = arow[2 * p[l]], ai = arow[2 * p[l] + 1];
-                const double mr = minors[2 * ((size_t)st.minor_off + l)];
-                const double mi = minors[2 * ((size_t)st.minor_off + l) + 1];
+                const size_t q = slot[st.minor_off + l];
+                const double mr = minors[2 * q];
+                const double mi = minors[2 * q + 1];
                 sr = __builtin_fma(ar, mr, sr);
                 sr = __builtin_fma(-ai, mi, sr);
                 si = __builtin_fma(ar, mi, si);
@@ -99,11 +101,11 @@ hipError_t launch_build_job_matrix(const double* U, int m, const int32_t* cols, 
     return hipGetLastError();
 }
 
-hipError_t launch_cc_weights(uint32_t nsteps, const CCStep* steps, const int32_t* pi, const double* minors,
-                             int32_t* drawn, double* wsum, hipStream_t s)
+hipError_t launch_cc_weights(uint32_t nsteps, const CCStep* steps, const int32_t* pi, const uint32_t* slot,
+                             const double* minors, int32_t* drawn, double* wsum, hipStream_t s)
 {
     if (nsteps == 0) return hipSuccess;
-    hipLaunchKernelGGL(cc_weights_kernel, dim3(nsteps), dim3(kCCThreads), 0, s, steps, pi, minors, drawn, wsum);
+    hipLaunchKernelGGL(cc_weights_kernel, dim3(nsteps), dim3(kCCThreads), 0, s, steps, pi, slot, minors, drawn, wsum);
     return hipGetLastError();
 }
 

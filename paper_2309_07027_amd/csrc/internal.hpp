@@ -57,9 +57,26 @@ struct PermDesc {
     uint32_t Q;              // Gray block length
     uint32_t lane_product;   // number of valid lane indices
     uint32_t groups;         // lane groups
-    double scale;            // 2^{1-n}
+    double scale;            // 2^{1-n} of the permanents computed (n - 1 columns of them for minors)
     double err_coeff;        // u * (n + sqrt(Q)), u the unit roundoff: error estimate = kappa * err_coeff
+    uint64_t part_base;      // first partial slot; unit u, target t -> part_base + u * max(1, targets) + t
+    uint32_t targets;        // 0: one permanent of the n columns.  G > 0: the G permanents that each
+                             //   leave out one of the last G columns (Laplace minors)
+    uint32_t res_base;       // index of the first result
 };
+
+// Leave-one-column-out walks over K columns cover the targets in groups of
+// minor_group(K): one group keeps K column sums, G prefix products and G
+// accumulators per lane (4K + 8G FP64 registers), so the group size shrinks as
+// K grows to keep two wavefronts per SIMD.
+constexpr int minor_group(int K)
+{
+    int gmax = 27 - K / 2;
+    if (gmax < 1) gmax = 1;
+    if (gmax > K) gmax = K;
+    const int groups = (K + gmax - 1) / gmax;
+    return (K + groups - 1) / groups;
+}
 
 // Sizes of the partial record of one unit: a complex double-double (4 doubles)
 // plus the sum of |addend| (1 double).

@@ -163,15 +163,15 @@ int walk_slots(Context& c, int n, int f32, uint64_t* slots)
     return BBFG_OK;
 }
 
-int batch_waves(Context& c, int bucket, int f32, int* waves)
+int batch_waves(Context& c, int bucket, int kind, int* waves)
 {
-    const auto key = std::make_pair(bucket, f32);
+    const auto key = std::make_pair(bucket, kind);
     auto it = c.occ_batch.find(key);
     if (it != c.occ_batch.end()) {
         *waves = it->second;
         return BBFG_OK;
     }
-    const void* fn = walk_batch_fn(bucket, f32);
+    const void* fn = kind == kKindMinors ? walk_minors_fn(bucket) : walk_batch_fn(bucket, kind);
     if (!fn) return set_error(BBFG_ERANGE, "no batch kernel for bucket %d", bucket);
     int blocks = 0;
     BBFG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, kWave, 0));
@@ -288,6 +288,14 @@ int run_perms(Context& c, std::vector<PermItem>& items, int f32, bool single, do
     if (nitem == 0) return BBFG_OK;
     if (single && nitem != 1) return set_error(BBFG_EINVAL, "internal: single launch with %zu items", nitem);
     hipStream_t s = current_stream();
+    // leave-one-column-out items (targets > 0) run in their own launches
+    const bool minors = items[0].targets > 0;
+    for (auto& it : items)
+        if ((it.targets > 0) != minors || (minors && (single || f32 || it.targets > it.plan->n + 1)))
+            return set_error(BBFG_EINVAL, "internal: bad mix of minor items");
+    // columns held per item: the plan's n, plus the left-out column for minors
+    auto cols_of = [&](const PermItem& it) { return it.plan->n + (it.targets > 0 ? 1 : 0); };
+    auto stride_of = [](const PermItem& it) { return (uint64_t)(it.targets > 0 ? it.targets : 1); };
 
     // distinct plans (row records are shared between equal shapes; Gray tables
     // are resident on the device and shared between equal low radices)
@@ -303,10 +311,11 @@ int run_perms(Context& c, std::vector<PermItem>& items, int f32, bool single, do
             plan_slot[p] = {n_rowinfo, dt};
             n_rowinfo += (size_t)p->r;
         }
+        const int nc = cols_of(it);
         n_srcrow += (size_t)p->r;
-        if (it.col_map) n_srccol += (size_t)p->n;
-        a_elems += (uint64_t)p->r * (uint64_t)p->n * 3u;  // a (r x n) + a2 (2r x n)
-        nmax = std::max(nmax, p->n);
+        if (it.col_map) n_srccol += (size_t)nc;
+        a_elems += (uint64_t)p->r * (uint64_t)nc * 3u;  // a (r x n) + a2 (2r x n)
+        nmax = std::max(nmax, nc);
     }
 
     // unit numbering: longest units first (items ordered by per-unit cost)
@@ -315,17 +324,29 @@ int run_perms(Context& c, std::vector<PermItem>& items, int f32, bool single, do
     if (!single) {
         auto cost = [&](size_t i) {
             const HostPlan& p = *items[i].plan;
-            return (double)p.span / (double)p.units_per_group * (6.0 * p.n - 2.0);
+            const double nc = cols_of(items[i]);
+            return (double)p.span / (double)p.units_per_group * (6.0 * nc - 2.0 + 12.0 * items[i].targets);
         };
         std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return cost(x) > cost(y); });
     }
-    std::vector<uint64_t> unit_base(nitem);
-    uint64_t total_units = 0;
+    std::vector<uint64_t> unit_base(nitem), part_base(nitem);
+    uint64_t total_units = 0, total_parts = 0;
     for (size_t oi = 0; oi < nitem; ++oi) {
+        const PermItem& it = items[order[oi]];
         unit_base[order[oi]] = total_units;
-        total_units += items[order[oi]].plan->units;
+        part_base[order[oi]] = total_parts;
+        total_units += it.plan->units;
+        total_parts += it.plan->units * stride_of(it);
     }
     if (total_units > 0xFFFFFFF0ull) return set_error(BBFG_ERANGE, "too many work units (%llu)", (unsigned long long)total_units);
+    // results: one per plain item, `targets` per minor item (item order)
+    std::vector<uint32_t> res_base(nitem);
+    uint64_t nres = 0;
+    for (size_t i = 0; i < nitem; ++i) {
+        res_base[i] = (uint32_t)nres;
+        nres += stride_of(items[i]);
+    }
+    if (nres > 0x7FFFFFFFull) return set_error(BBFG_ERANGE, "too many results (%llu)", (unsigned long long)nres);
 
     // host metadata image
     Layout L;
@@ -335,6 +356,7 @@ int run_perms(Context& c, std::vector<PermItem>& items, int f32, bool single, do
     const size_t off_src = L.add(sizeof(uint32_t) * std::max<size_t>(1, n_srcrow));
     const size_t off_col = L.add(sizeof(uint32_t) * std::max<size_t>(1, n_srccol));
     const size_t off_uitem = single ? 0 : L.add(sizeof(uint32_t) * (size_t)total_units);
+    const size_t off_ritem = L.add(sizeof(uint32_t) * (size_t)nres);
     BBFG_TRY(c.hmeta.ensure(L.size));
     BBFG_TRY(c.meta.ensure(L.size));
     char* H = c.hmeta.as<char>();
@@ -343,6 +365,7 @@ int run_perms(Context& c, std::vector<PermItem>& items, int f32, bool single, do
     PrepItem* hp = reinterpret_cast<PrepItem*>(H + off_prep);
     uint32_t* hs = reinterpret_cast<uint32_t*>(H + off_src);
     uint32_t* hc = reinterpret_cast<uint32_t*>(H + off_col);
+    uint32_t* hri = reinterpret_cast<uint32_t*>(H + off_ritem);
     for (const auto& kv : plan_slot)
         std::memcpy(hr + kv.second.first, kv.first->rows.data(), sizeof(RowInfo) * (size_t)kv.first->r);
     uint64_t a_cursor = 0;
@@ -350,24 +373,29 @@ int run_perms(Context& c, std::vector<PermItem>& items, int f32, bool single, do
     for (size_t i = 0; i < nitem; ++i) {
         const HostPlan& p = *items[i].plan;
         const auto sl = plan_slot[&p];
+        const int nc = cols_of(items[i]);
         PermDesc& d = hd[i];
         std::memset(&d, 0, sizeof d);
         d.a_off = a_cursor;
-        d.a2_off = a_cursor + (uint64_t)p.r * p.n;
-        a_cursor += (uint64_t)p.r * p.n * 3u;
+        d.a2_off = a_cursor + (uint64_t)p.r * nc;
+        a_cursor += (uint64_t)p.r * nc * 3u;
         d.tab = sl.second;
         d.unit_base = unit_base[i];
         d.units = p.units;
         d.units_per_group = p.units_per_group;
         d.span = p.span;
         d.rowinfo_off = (uint32_t)sl.first;
-        d.n = p.n;
+        d.n = nc;
         d.r = p.r;
         d.Q = p.Q;
         d.lane_product = p.lane_product;
         d.groups = p.groups;
         d.scale = std::ldexp(1.0, 1 - p.n);
         d.err_coeff = p.err_coeff * (f32 ? 0x1.0p-24 : 0x1.0p-53);
+        d.part_base = part_base[i];
+        d.targets = (uint32_t)items[i].targets;
+        d.res_base = res_base[i];
+        for (uint64_t t = 0; t < stride_of(items[i]); ++t) hri[res_base[i] + t] = (uint32_t)i;
         PrepItem& q = hp[i];
         std::memset(&q, 0, sizeof q);
         q.src = items[i].src;
@@ -376,7 +404,7 @@ int run_perms(Context& c, std::vector<PermItem>& items, int f32, bool single, do
         q.a_off = d.a_off;
         q.a2_off = d.a2_off;
         q.srcrow_off = (uint32_t)s_cursor;
-        q.n = p.n;
+        q.n = nc;
         q.r = p.r;
         q.f32 = f32;
         for (int k = 0; k < p.r; ++k) {
@@ -385,7 +413,7 @@ int run_perms(Context& c, std::vector<PermItem>& items, int f32, bool single, do
         }
         if (items[i].col_map) {
             q.srccol_off = (uint32_t)c_cursor;
-            for (int j = 0; j < p.n; ++j) hc[c_cursor++] = (uint32_t)items[i].col_map[j];
+            for (int j = 0; j < nc; ++j) hc[c_cursor++] = (uint32_t)items[i].col_map[j];
         } else {
             q.srccol_off = kIdentityCols;
         }
@@ -398,9 +426,9 @@ int run_perms(Context& c, std::vector<PermItem>& items, int f32, bool single, do
     // device buffers
     if (f32) BBFG_TRY(c.arena_f.ensure(sizeof(float) * 2 * std::max<uint64_t>(1, a_elems)));
     else BBFG_TRY(c.arena_d.ensure(sizeof(double) * 2 * std::max<uint64_t>(1, a_elems)));
-    BBFG_TRY(c.partials.ensure(sizeof(double) * kPartialDoubles * (size_t)total_units));
-    BBFG_TRY(c.results.ensure(sizeof(double) * 4 * nitem));
-    BBFG_TRY(c.hres.ensure(sizeof(double) * 4 * nitem));
+    BBFG_TRY(c.partials.ensure(sizeof(double) * kPartialDoubles * (size_t)total_parts));
+    BBFG_TRY(c.results.ensure(sizeof(double) * 4 * (size_t)nres));
+    BBFG_TRY(c.hres.ensure(sizeof(double) * 4 * (size_t)nres));
     char* D = c.meta.as<char>();
 
     WalkArgs W;
@@ -423,7 +451,7 @@ int run_perms(Context& c, std::vector<PermItem>& items, int f32, bool single, do
         bucket = batch_bucket_max(nmax, f32);
         if (bucket < 0) return set_error(BBFG_ERANGE, "no batch kernel for n=%d", nmax);
         int waves = 1;
-        BBFG_TRY(batch_waves(c, bucket, f32, &waves));
+        BBFG_TRY(batch_waves(c, bucket, minors ? kKindMinors : f32, &waves));
         grid = std::min<uint64_t>((uint64_t)waves * (uint64_t)c.n_cu, total_units);
     }
     double* R = c.results.as<double>();
@@ -441,10 +469,12 @@ int run_perms(Context& c, std::vector<PermItem>& items, int f32, bool single, do
         if (!single) BBFG_HIP(launch_reset_counter(W.counter, q));
         if (timed) BBFG_HIP(hipEventRecord(c.ev0, q));
         if (single) BBFG_HIP(launch_walk_single(items[0].plan->n, f32, (uint32_t)total_units, q, W, 0u));
+        else if (minors) BBFG_HIP(launch_walk_minors(bucket, (uint32_t)grid, q, W));
         else BBFG_HIP(launch_walk_batch(bucket, f32, (uint32_t)grid, q, W));
         if (timed) BBFG_HIP(hipEventRecord(c.ev1, q));
-        BBFG_HIP(launch_finalize((uint32_t)nitem, q, W.descs, W.partials, R, R + 2 * nitem));
-        if (sync) BBFG_HIP(hipMemcpyAsync(HR, R, sizeof(double) * 4 * nitem, hipMemcpyDeviceToHost, q));
+        BBFG_HIP(launch_finalize((uint32_t)nres, q, W.descs, reinterpret_cast<const uint32_t*>(D + off_ritem),
+                                 W.partials, R, R + 2 * nres));
+        if (sync) BBFG_HIP(hipMemcpyAsync(HR, R, sizeof(double) * 4 * nres, hipMemcpyDeviceToHost, q));
         return BBFG_OK;
     };
 
@@ -461,9 +491,10 @@ int run_perms(Context& c, std::vector<PermItem>& items, int f32, bool single, do
             for (size_t i = 0; i < n; ++i) key = (key ^ b[i]) * 1099511628211ull;
         };
         mix(&W, sizeof W);
-        const uint64_t extra[] = {nitem, (uint64_t)single, (uint64_t)f32, (uint64_t)bucket, grid, L.size, off_desc, off_row, off_prep,
-                                  off_src, off_col, off_uitem, (uint64_t)(uintptr_t)H, (uint64_t)(uintptr_t)D,
-                                  (uint64_t)(uintptr_t)R, (uint64_t)(uintptr_t)HR, (uint64_t)(uintptr_t)c.arena_d.p,
+        const uint64_t extra[] = {nitem, nres, (uint64_t)single, (uint64_t)minors, (uint64_t)f32, (uint64_t)bucket,
+                                  grid, L.size, off_desc, off_row, off_prep, off_src, off_col, off_uitem, off_ritem,
+                                  (uint64_t)(uintptr_t)H, (uint64_t)(uintptr_t)D, (uint64_t)(uintptr_t)R,
+                                  (uint64_t)(uintptr_t)HR, (uint64_t)(uintptr_t)c.arena_d.p,
                                   (uint64_t)(uintptr_t)c.arena_f.p};
         mix(extra, sizeof extra);
         auto git = c.graphs.find(key);
@@ -501,8 +532,8 @@ int run_perms(Context& c, std::vector<PermItem>& items, int f32, bool single, do
     if (rr) rr->units = total_units;
     if (!sync) return BBFG_OK;
     BBFG_HIP(hipStreamSynchronize(s));
-    if (out_host) std::memcpy(out_host, HR, sizeof(double) * 2 * nitem);
-    if (diag_host) std::memcpy(diag_host, HR + 2 * nitem, sizeof(double) * 2 * nitem);
+    if (out_host) std::memcpy(out_host, HR, sizeof(double) * 2 * nres);
+    if (diag_host) std::memcpy(diag_host, HR + 2 * nres, sizeof(double) * 2 * nres);
     if (rr) {
         float ms = 0.f;
         BBFG_HIP(hipEventElapsedTime(&ms, c.ev0, c.ev1));

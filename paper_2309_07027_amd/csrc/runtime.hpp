@@ -81,7 +81,7 @@ struct Context {
     PinnedBuf hmeta, hres, cc_hmeta;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     std::map<std::pair<int, int>, int> occ_single;  // (n, f32) -> waves per CU
-    std::map<std::pair<int, int>, int> occ_batch;   // (bucket, f32) -> waves per CU
+    std::map<std::pair<int, int>, int> occ_batch;   // (bucket, kind) -> waves per CU
     std::unordered_map<std::string, std::shared_ptr<const HostPlan>> plans;
     // Gray tables shared between plans (host), and their device copies:
     // bump-allocated in chunks that are never moved while referenced
@@ -111,7 +111,10 @@ hipStream_t current_stream();
 void set_current_stream(hipStream_t s);
 
 int walk_slots(Context& c, int n, int f32, uint64_t* slots);
-int batch_waves(Context& c, int bucket, int f32, int* waves);
+// Resident wavefronts per CU of a batch kernel: kind = 0 (FP64), 1 (FP32) or
+// kKindMinors (leave-one-column-out walks).
+constexpr int kKindMinors = 2;
+int batch_waves(Context& c, int bucket, int kind, int* waves);
 int get_plan(Context& c, const int32_t* mult, int n_rows, int n_cols, int f32, int mode,
              std::shared_ptr<const HostPlan>* out);
 // Device copy of a plan's Gray table (uploaded on first use, then resident).
@@ -141,6 +144,10 @@ struct PermItem {
     const int32_t* mult = nullptr;
     const int32_t* row_map = nullptr;
     const int32_t* col_map = nullptr;
+    // 0: perm of the n columns.  G > 0: the matrix has n + 1 columns (col_map
+    // lists n + 1) and the item yields the G permanents that each leave out one
+    // of its last G columns; the plan is that of the n-column permanents.
+    int targets = 0;
     std::shared_ptr<const HostPlan> plan;
 };
 
@@ -151,8 +158,9 @@ struct RunResult {
 };
 
 // Evaluates items (all n >= 1).  The (re, im) results stay in c.results (item
-// order) and, when out_host is not null, are copied to out_host[2*i]; the
-// diagnostics (err_est, kappa) to diag_host[2*i].  With sync = false nothing is
+// order; an item with targets = G has G consecutive results) and, when out_host
+// is not null, are copied to out_host[2*i]; the diagnostics (err_est, kappa) to
+// diag_host[2*i] (zero for minor items, whose magnitude sums are not formed).  With sync = false nothing is
 // copied back and the stream is not synchronised (the caller queues more work
 // that reads c.results).  single = true uses the one-permanent launch.
 // use_graph = true captures a layout into a hipGraph the second time it is

@@ -124,6 +124,32 @@ void finish_sample(CCJob& job, int s)
 
 }  // namespace
 
+void add_minor_items(const PermItem& proto, const int32_t* cols, std::deque<std::vector<int32_t>>& keep,
+                     std::vector<PermItem>& items, uint64_t res_first, uint32_t* slot)
+{
+    const int K = proto.plan->n + 1;
+    const int G = minor_group(K);
+    const int groups = (K + G - 1) / G;
+    uint64_t res = res_first;
+    for (int gi = 0; gi < groups; ++gi) {
+        // targets [t0, t0 + G); the last group may reach back into the previous
+        // one, whose results own those columns
+        const int t0 = std::min(gi * G, K - G);
+        keep.emplace_back();
+        std::vector<int32_t>& cm = keep.back();
+        for (int l = 0; l < K; ++l)
+            if (l < t0 || l >= t0 + G) cm.push_back(cols[l]);
+        for (int l = t0; l < t0 + G; ++l) cm.push_back(cols[l]);
+        PermItem it = proto;
+        it.col_map = cm.data();
+        it.targets = G;
+        items.push_back(std::move(it));
+        for (int t = 0; t < G; ++t)
+            if (t0 + t >= gi * G) slot[t0 + t] = (uint32_t)(res + (uint64_t)t);
+        res += (uint64_t)G;
+    }
+}
+
 int cc_step(Context& c, std::vector<ActiveSample>& act, double* kernel_ms, uint64_t* addends)
 {
     hipStream_t s = current_stream();
@@ -131,7 +157,9 @@ int cc_step(Context& c, std::vector<ActiveSample>& act, double* kernel_ms, uint6
     std::deque<std::vector<int32_t>> keep;  // multiplicities, row and column maps (stable addresses)
     std::vector<CCStep> steps;
     std::vector<int32_t> pis;
+    std::vector<uint32_t> slots;            // result index of each minor
     std::vector<size_t> act_of_step;
+    uint64_t nres = 0;
     for (size_t ai = 0; ai < act.size(); ++ai) {
         CCJob& J = *act[ai].job;
         CCSample& S = J.samples[(size_t)act[ai].s];
@@ -148,6 +176,7 @@ int cc_step(Context& c, std::vector<ActiveSample>& act, double* kernel_ms, uint6
         const uint64_t x = splitmix64_draw(S.key, (uint64_t)(J.n - 1 + (k - 1)));
         st.u = (double)(x >> 11) * 0x1.0p-53;
         if (k >= 2) {
+            // the k minors share the prefix rows: one joint walk over k columns
             std::map<int32_t, int32_t> cnt;
             for (int32_t r : S.prefix) cnt[r]++;
             keep.emplace_back();
@@ -158,27 +187,21 @@ int cc_step(Context& c, std::vector<ActiveSample>& act, double* kernel_ms, uint6
                 rowmap.push_back(kv.first);
                 mult.push_back(kv.second);
             }
-            std::shared_ptr<const HostPlan> plan;
-            BBFG_TRY(get_plan(c, mult.data(), (int)mult.size(), k - 1, 0, PLAN_BATCH, &plan));
-            st.minor_off = (uint32_t)items.size();
-            for (int l = 0; l < k; ++l) {
-                keep.emplace_back();
-                std::vector<int32_t>& colmap = keep.back();
-                for (int b = 0; b < k; ++b)
-                    if (b != l) colmap.push_back(S.pi[(size_t)b]);
-                PermItem it;
-                it.src = J.A.as<double>();
-                it.src_off = 0;
-                it.ld = (uint32_t)J.n;
-                it.n_rows = (int)mult.size();
-                it.n = k - 1;
-                it.mult = mult.data();
-                it.row_map = rowmap.data();
-                it.col_map = colmap.data();
-                it.plan = plan;
-                if (addends) *addends += plan->n_addends;
-                items.push_back(std::move(it));
-            }
+            PermItem proto;
+            BBFG_TRY(get_plan(c, mult.data(), (int)mult.size(), k - 1, 0, PLAN_BATCH, &proto.plan));
+            proto.src = J.A.as<double>();
+            proto.src_off = 0;
+            proto.ld = (uint32_t)J.n;
+            proto.n_rows = (int)mult.size();
+            proto.n = k - 1;
+            proto.mult = mult.data();
+            proto.row_map = rowmap.data();
+            st.minor_off = (uint32_t)slots.size();
+            slots.resize(slots.size() + (size_t)k);
+            const size_t first = items.size();
+            add_minor_items(proto, S.pi.data(), keep, items, nres, slots.data() + st.minor_off);
+            for (size_t i = first; i < items.size(); ++i) nres += (uint64_t)items[i].targets;
+            if (addends) *addends += (uint64_t)k * proto.plan->n_addends;
         }
         steps.push_back(st);
         act_of_step.push_back(ai);
@@ -190,6 +213,7 @@ int cc_step(Context& c, std::vector<ActiveSample>& act, double* kernel_ms, uint6
     Layout L;
     const size_t o_steps = L.add(sizeof(CCStep) * steps.size());
     const size_t o_pi = L.add(sizeof(int32_t) * pis.size());
+    const size_t o_slot = L.add(sizeof(uint32_t) * std::max<size_t>(1, slots.size()));
     const size_t o_drawn = L.add(sizeof(int32_t) * steps.size());
     const size_t o_wsum = L.add(sizeof(double) * steps.size());
     BBFG_TRY(c.cc_hmeta.ensure(L.size));
@@ -198,9 +222,11 @@ int cc_step(Context& c, std::vector<ActiveSample>& act, double* kernel_ms, uint6
     char* D = c.cc_meta.as<char>();
     std::memcpy(H + o_steps, steps.data(), sizeof(CCStep) * steps.size());
     std::memcpy(H + o_pi, pis.data(), sizeof(int32_t) * pis.size());
+    if (!slots.empty()) std::memcpy(H + o_slot, slots.data(), sizeof(uint32_t) * slots.size());
     BBFG_HIP(hipMemcpyAsync(D, H, o_drawn, hipMemcpyHostToDevice, s));
     BBFG_HIP(launch_cc_weights((uint32_t)steps.size(), reinterpret_cast<const CCStep*>(D + o_steps),
-                               reinterpret_cast<const int32_t*>(D + o_pi), c.results.as<double>(),
+                               reinterpret_cast<const int32_t*>(D + o_pi),
+                               reinterpret_cast<const uint32_t*>(D + o_slot), c.results.as<double>(),
                                reinterpret_cast<int32_t*>(D + o_drawn), reinterpret_cast<double*>(D + o_wsum), s));
     BBFG_HIP(hipMemcpyAsync(H + o_drawn, D + o_drawn, L.size - o_drawn, hipMemcpyDeviceToHost, s));
     BBFG_HIP(hipStreamSynchronize(s));

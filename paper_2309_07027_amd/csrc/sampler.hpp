@@ -3,6 +3,7 @@
 #pragma once
 
 #include <cstdint>
+#include <deque>
 #include <vector>
 
 #include "runtime.hpp"
@@ -41,6 +42,15 @@ struct ActiveSample {
     CCJob* job;
     int s;
 };
+
+// Appends the items of one leave-one-column-out walk: the K = proto.plan->n + 1
+// columns cols[0..K) (source columns of the matrix of proto), in groups of
+// minor_group(K) targets; each group's column map lists its other columns first
+// and its targets last.  The items' results follow result index res_first in
+// item order; slot[l] receives the result index of the permanent without
+// column l.  Column maps are kept alive in `keep`.
+void add_minor_items(const PermItem& proto, const int32_t* cols, std::deque<std::vector<int32_t>>& keep,
+                     std::vector<PermItem>& items, uint64_t res_first, uint32_t* slot);
 
 // Host validation of sampling arguments (no device work).
 int cc_validate(const void* U, int m, const int32_t* occ, int n_samples, double loss);

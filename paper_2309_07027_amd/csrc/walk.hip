@@ -24,6 +24,7 @@
 #include "internal.hpp"
 #include "kernels.hpp"
 #include "walk_core.hpp"
+#include "walk_device.hpp"
 
 namespace bbfg {
 
@@ -81,29 +82,6 @@ __global__ void prep_rows_kernel(const PrepItem* __restrict__ items, const uint3
     }
 }
 
-// the same bits), then lane 0 stores the unit's partial record.
-__device__ __forceinline__ void store_partial(double* partials, uint64_t slot, double r, double i, double a)
-{
-    ddv sr = {r, 0.0}, si = {i, 0.0};
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-        ddv orr = {__shfl_xor(sr.hi, off), __shfl_xor(sr.lo, off)};
-        ddv oi = {__shfl_xor(si.hi, off), __shfl_xor(si.lo, off)};
-        const double oa = __shfl_xor(a, off);
-        sr = dd_add(sr, orr);
-        si = dd_add(si, oi);
-        a = a + oa;
-    }
-    if ((threadIdx.x & (kWave - 1)) == 0) {
-        double* p = partials + slot * kPartialDoubles;
-        p[0] = sr.hi;
-        p[1] = sr.lo;
-        p[2] = si.hi;
-        p[3] = si.lo;
-        p[4] = a;
-    }
-}
-
 // ---------------------------------------------------------------------------
 // single-permanent launch: one wavefront per unit, grid = units
 // ---------------------------------------------------------------------------
@@ -114,7 +92,7 @@ __global__ __launch_bounds__(kWave) void walk_single_kernel(WalkArgs A, uint32_t
     const uint32_t u = blockIdx.x;
     double r, i, a;
     walk_unit<N, Real>(A, d, u, threadIdx.x & (kWave - 1), r, i, a);
-    store_partial(A.partials, d.unit_base + u, r, i, a);
+    store_partial(A.partials, d.part_base + u, r, i, a);
 }
 
 // ---------------------------------------------------------------------------
@@ -132,28 +110,6 @@ __device__ __forceinline__ void dispatch_unit(const WalkArgs& A, const PermDesc&
             dispatch_unit<NMIN + 1, NMAX, Real>(A, d, u_local, r, i, a);
         }
     }
-}
-
-// Every lane of the wavefront stores the same partial record (the butterfly
-// leaves identical bits in all lanes), so the store needs no divergent branch.
-__device__ __forceinline__ void store_partial_all_lanes(double* partials, uint64_t slot, double r, double i, double a)
-{
-    ddv sr = {r, 0.0}, si = {i, 0.0};
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-        ddv orr = {__shfl_xor(sr.hi, off), __shfl_xor(sr.lo, off)};
-        ddv oi = {__shfl_xor(si.hi, off), __shfl_xor(si.lo, off)};
-        const double oa = __shfl_xor(a, off);
-        sr = dd_add(sr, orr);
-        si = dd_add(si, oi);
-        a = a + oa;
-    }
-    double* p = partials + slot * kPartialDoubles;
-    p[0] = sr.hi;
-    p[1] = sr.lo;
-    p[2] = si.hi;
-    p[3] = si.lo;
-    p[4] = a;
 }
 
 // The loop control is kept free of divergent branches: lane 0 takes the next
@@ -174,7 +130,7 @@ __global__ __launch_bounds__(kWave) void walk_batch_kernel(WalkArgs A)
         const uint32_t u_local = u - (uint32_t)d.unit_base;
         double r = 0.0, i = 0.0, a = 0.0;
         dispatch_unit<1, NMAX, Real>(A, d, u_local, r, i, a);
-        store_partial_all_lanes(A.partials, u, r, i, a);
+        store_partial_all_lanes(A.partials, d.part_base + u_local, r, i, a);
     }
 }
 
@@ -188,15 +144,19 @@ __global__ void reset_counter_kernel(uint32_t* counter)
 // ---------------------------------------------------------------------------
 constexpr int kFinThreads = 256;
 
+// One block per result: result b belongs to item res_item[b], target b - res_base.
 __global__ __launch_bounds__(kFinThreads) void finalize_kernel(const PermDesc* __restrict__ descs,
+                                                               const uint32_t* __restrict__ res_item,
                                                                const double* __restrict__ partials,
                                                                double* __restrict__ out, double* __restrict__ diag)
 {
-    const PermDesc d = descs[blockIdx.x];
+    const PermDesc d = descs[res_item[blockIdx.x]];
+    const uint64_t stride = d.targets ? d.targets : 1u;
+    const uint64_t target = blockIdx.x - d.res_base;
     ddv sr = {0.0, 0.0}, si = {0.0, 0.0};
     double sa = 0.0;
     for (uint64_t u = threadIdx.x; u < d.units; u += kFinThreads) {
-        const double* p = partials + (d.unit_base + u) * kPartialDoubles;
+        const double* p = partials + (d.part_base + u * stride + target) * kPartialDoubles;
         sr = dd_add(sr, {p[0], p[1]});
         si = dd_add(si, {p[2], p[3]});
         sa += p[4];
@@ -292,6 +252,25 @@ const void* walk_batch_fn(int bucket, int f32)
     }
 }
 
+const void* walk_minors_fn(int bucket)
+{
+    switch (bucket) {
+    case 16: return walk_minors_fn_b16();
+    case 24: return walk_minors_fn_b24();
+    case 32: return walk_minors_fn_b32();
+    case 48: return walk_minors_fn_b48();
+    default: return nullptr;
+    }
+}
+
+hipError_t launch_walk_minors(int bucket, uint32_t grid, hipStream_t s, const WalkArgs& A)
+{
+    const void* fn = walk_minors_fn(bucket);
+    if (!fn) return hipErrorInvalidValue;
+    void* args[] = {const_cast<WalkArgs*>(&A)};
+    return hipLaunchKernel(fn, dim3(grid), dim3(kWave), args, 0, s);
+}
+
 hipError_t launch_walk_single(int n, int f32, uint32_t grid, hipStream_t s, const WalkArgs& A, uint32_t item)
 {
     const void* fn = walk_single_fn(n, f32);
@@ -322,11 +301,11 @@ hipError_t launch_prep(uint32_t items, hipStream_t s, const PrepItem* it, const 
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(uint32_t items, hipStream_t s, const PermDesc* descs, const double* partials, double* out,
-                           double* diag)
+hipError_t launch_finalize(uint32_t results, hipStream_t s, const PermDesc* descs, const uint32_t* res_item,
+                           const double* partials, double* out, double* diag)
 {
-    if (items == 0) return hipSuccess;
-    hipLaunchKernelGGL(finalize_kernel, dim3(items), dim3(kFinThreads), 0, s, descs, partials, out, diag);
+    if (results == 0) return hipSuccess;
+    hipLaunchKernelGGL(finalize_kernel, dim3(results), dim3(kFinThreads), 0, s, descs, res_item, partials, out, diag);
     return hipGetLastError();
 }
 

@@ -71,6 +71,16 @@ BBFG_FN ddv dd_add(ddv a, ddv b)
 BBFG_FN float fmar(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 BBFG_FN double fmar(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
+// complex product (a_r + i a_i)(b_r + i b_i): two products, two fused
+template <typename Real>
+BBFG_FN void cmul(Real ar, Real ai, Real br, Real bi, Real& cr, Real& ci)
+{
+    const Real t0 = ai * bi;
+    const Real t1 = ai * br;
+    cr = fmar(ar, br, -t0);
+    ci = fmar(ar, bi, t1);
+}
+
 // ---------------------------------------------------------------------------
 // product of N complex column sums: four independent chains, then a tree
 // ---------------------------------------------------------------------------
@@ -243,6 +253,106 @@ BBFG_FN void walk_unit(const WalkArgs& A, const PermDesc& d, uint32_t u_local, u
     out_r = accr;
     out_i = acci;
     out_a = acca;
+}
+
+// Leave-one-column-out products of one addend, accumulated: with c_j the K
+// column sums and T = K - G, for every target t < G
+//   acc[t] += ws * prod_{j != T + t} c_j
+// = ws * (prod_{j < T} c_j) * (prod_{i < t} c_{T+i}) * (prod_{t < i < G} c_{T+i}):
+// one product of the leading sums, prefix products over the targets, and a
+// running suffix product (about K + 2G complex products for G permanents).
+template <int K, int G, typename Real>
+BBFG_FN void minors_accumulate(const Real* re, const Real* im, double ws, double* accr, double* acci)
+{
+    constexpr int T = K - G;
+    Real pr[G], pim[G];
+    if constexpr (T > 0) {
+        cprod<T, Real>(re, im, pr[0], pim[0]);
+    } else {
+        pr[0] = Real(1);
+        pim[0] = Real(0);
+    }
+#pragma unroll
+    for (int t = 1; t < G; ++t) cmul<Real>(pr[t - 1], pim[t - 1], re[T + t - 1], im[T + t - 1], pr[t], pim[t]);
+    Real sr = Real(1), si = Real(0);
+#pragma unroll
+    for (int t = G - 1; t >= 0; --t) {
+        Real xr, xi;
+        if (t == G - 1) {
+            xr = pr[t];
+            xi = pim[t];
+        } else {
+            cmul<Real>(pr[t], pim[t], sr, si, xr, xi);
+        }
+        accr[t] = __builtin_fma(ws, (double)xr, accr[t]);
+        acci[t] = __builtin_fma(ws, (double)xi, acci[t]);
+        if (t > 0) {
+            if (t == G - 1) {
+                sr = re[T + t];
+                si = im[T + t];
+            } else {
+                Real nr, ni;
+                cmul<Real>(sr, si, re[T + t], im[T + t], nr, ni);
+                sr = nr;
+                si = ni;
+            }
+        }
+    }
+}
+
+// One work unit of a leave-one-column-out walk (d.targets == G): the lane's
+// sums over its addends of w(Delta) * prod_{j != K-G+t} c_j(Delta), t < G, i.e.
+// of the permanents (size K - 1) that each drop one of the last G columns.
+// The walk over the rows is the one of walk_unit; the signed weight w * s is
+// an integer below 2^53 (a product of binomials), hence exact.
+template <int K, int G, typename Real>
+BBFG_FN void walk_minors_unit(const WalkArgs& A, const PermDesc& d, uint32_t u_local, uint32_t lane, double* out_r,
+                              double* out_i)
+{
+    const uint32_t upg = (uint32_t)d.units_per_group;
+    const uint32_t g = u_local / upg;
+    const uint32_t part = u_local - g * upg;
+    const uint64_t base = d.span / upg;
+    const uint32_t rem = (uint32_t)(d.span - base * upg);
+    uint64_t lin = (uint64_t)part * base + (part < rem ? part : rem);
+    const uint64_t lin1 = lin + base + (part < rem ? 1u : 0u);
+    uint32_t lane_idx = g * kWave + lane;
+    const bool valid = lane_idx < d.lane_product;
+    if (!valid) lane_idx = 0;
+
+    kptr<TabEntry> tab = kconst(d.tab);
+    kptr<Real> a2 = kconst(RowsOf<Real>::a2(A) + 2 * d.a2_off);
+    const uint32_t Q = d.Q;
+
+#pragma unroll
+    for (int t = 0; t < G; ++t) {
+        out_r[t] = 0.0;
+        out_i[t] = 0.0;
+    }
+    Real re[K], im[K];
+    while (lin < lin1) {
+        const uint64_t h = lin / Q;
+        const uint32_t t0 = (uint32_t)(lin - h * Q);
+        const uint64_t bend = (h + 1) * (uint64_t)Q;
+        const uint32_t t1 = (uint32_t)(((lin1 < bend) ? lin1 : bend) - h * Q);
+        double w;
+        seed<K, Real>(A, d, lane_idx, h, t0, re, im, w);
+        if (!valid) w = 0.0;
+        for (uint32_t t = t0; t < t1; ++t) {
+            if (t > t0) {
+                const uint32_t rowi = uniform_u32(tab[t].row);
+                kptr<Real> row = a2 + 2 * (size_t)rowi * K;
+#pragma unroll
+                for (int j = 0; j < K; ++j) {
+                    re[j] += row[2 * j];
+                    im[j] += row[2 * j + 1];
+                }
+            }
+            const double ws = w * tab[t].s;
+            minors_accumulate<K, G, Real>(re, im, ws, out_r, out_i);
+        }
+        lin += (uint64_t)(t1 - t0);
+    }
 }
 
 }  // namespace bbfg

@@ -1,0 +1,59 @@
+// walk_device.hpp -- device-side reductions shared by the walk kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "internal.hpp"
+#include "walk_core.hpp"
+
+namespace bbfg {
+
+// Wavefront sum of the per-lane results in double-double (the butterfly leaves
+// the same bits in every lane), then lane 0 stores the unit's partial record.
+__device__ __forceinline__ void store_partial(double* partials, uint64_t slot, double r, double i, double a)
+{
+    ddv sr = {r, 0.0}, si = {i, 0.0};
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        ddv orr = {__shfl_xor(sr.hi, off), __shfl_xor(sr.lo, off)};
+        ddv oi = {__shfl_xor(si.hi, off), __shfl_xor(si.lo, off)};
+        const double oa = __shfl_xor(a, off);
+        sr = dd_add(sr, orr);
+        si = dd_add(si, oi);
+        a = a + oa;
+    }
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        double* p = partials + slot * kPartialDoubles;
+        p[0] = sr.hi;
+        p[1] = sr.lo;
+        p[2] = si.hi;
+        p[3] = si.lo;
+        p[4] = a;
+    }
+}
+
+// Every lane of the wavefront stores the same partial record (the butterfly
+// leaves identical bits in all lanes), so the store needs no divergent branch.
+__device__ __forceinline__ void store_partial_all_lanes(double* partials, uint64_t slot, double r, double i, double a)
+{
+    ddv sr = {r, 0.0}, si = {i, 0.0};
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        ddv orr = {__shfl_xor(sr.hi, off), __shfl_xor(sr.lo, off)};
+        ddv oi = {__shfl_xor(si.hi, off), __shfl_xor(si.lo, off)};
+        const double oa = __shfl_xor(a, off);
+        sr = dd_add(sr, orr);
+        si = dd_add(si, oi);
+        a = a + oa;
+    }
+    double* p = partials + slot * kPartialDoubles;
+    p[0] = sr.hi;
+    p[1] = sr.lo;
+    p[2] = si.hi;
+    p[3] = si.lo;
+    p[4] = a;
+}
+
+}  // namespace bbfg

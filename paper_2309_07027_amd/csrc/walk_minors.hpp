@@ -1,0 +1,58 @@
+// walk_minors.hpp -- gfx950 kernel of the batched leave-one-column-out walks
+// (the Laplace minors of the Clifford & Clifford step, Sec. 4, evaluated with
+// Eq. bbfgrepeated).  Each bucket (largest column count) is instantiated in a
+// translation unit of its own, walk_minors_b<bucket>.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "internal.hpp"
+#include "walk_core.hpp"
+#include "walk_device.hpp"
+
+namespace bbfg {
+
+// ---------------------------------------------------------------------------
+// batched leave-one-column-out walks (Laplace minors of the sampler step):
+// the same persistent loop; a unit of a K-column item yields minor_group(K)
+// partial records, one per target column
+// ---------------------------------------------------------------------------
+template <int K>
+__device__ __forceinline__ void minors_unit_store(const WalkArgs& A, const PermDesc& d, uint32_t u_local)
+{
+    constexpr int G = minor_group(K);
+    double r[G], i[G];
+    walk_minors_unit<K, G, double>(A, d, u_local, threadIdx.x & (kWave - 1), r, i);
+#pragma unroll
+    for (int t = 0; t < G; ++t)
+        store_partial_all_lanes(A.partials, d.part_base + (uint64_t)u_local * G + t, r[t], i[t], 0.0);
+}
+
+template <int KMIN, int KMAX>
+__device__ __forceinline__ void dispatch_minors(const WalkArgs& A, const PermDesc& d, uint32_t u_local)
+{
+    if constexpr (KMIN <= KMAX) {
+        if (d.n == KMIN) minors_unit_store<KMIN>(A, d, u_local);
+        else dispatch_minors<KMIN + 1, KMAX>(A, d, u_local);
+    }
+}
+
+template <int KMAX>
+__global__ __launch_bounds__(kWave) void walk_minors_batch_kernel(WalkArgs A)
+{
+    __shared__ uint32_t next_unit;
+    for (;;) {
+        if (threadIdx.x == 0) next_unit = atomicAdd(A.counter, 1u);
+        __syncthreads();
+        const uint32_t u = __builtin_amdgcn_readfirstlane(next_unit);
+        __syncthreads();
+        if (u >= A.total_units) break;
+        const uint32_t item = __builtin_amdgcn_readfirstlane(A.unit_item[u]);
+        const PermDesc d = A.descs[item];
+        dispatch_minors<2, KMAX>(A, d, u - (uint32_t)d.unit_base);
+    }
+}
+
+}  // namespace bbfg

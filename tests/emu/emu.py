@@ -29,7 +29,7 @@ def run(A, M, slots: int, f32: bool = False, l_batch: int = 0):
     unit length."""
     A = np.ascontiguousarray(np.asarray(A, dtype=np.complex128))
     r, n = A.shape
-    lines = [f"{r} {n} {int(slots)} {1 if f32 else 0} {int(l_batch)}", " ".join(str(int(m)) for m in M)]
+    lines = [f"{r} {n} {int(slots)} {1 if f32 else 0} {int(l_batch)} 0", " ".join(str(int(m)) for m in M)]
     lines.append(" ".join(f"{float(x.real).hex()} {float(x.imag).hex()}" for x in A.ravel()))
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0")
     p = subprocess.run([str(EXE)], input="\n".join(lines) + "\n", capture_output=True, text=True, env=env,
@@ -38,3 +38,18 @@ def run(A, M, slots: int, f32: bool = False, l_batch: int = 0):
         raise RuntimeError(f"walk_emu failed ({p.returncode}): {p.stderr[-2000:]}")
     re_, im_, err, kappa, units = p.stdout.split()
     return complex(float.fromhex(re_), float.fromhex(im_)), float.fromhex(err), float.fromhex(kappa), int(units)
+
+
+def run_minors(A, M, l_batch: int):
+    """Emulated batched minors walk: [perm(A without column l, M) for each l]."""
+    A = np.ascontiguousarray(np.asarray(A, dtype=np.complex128))
+    r, n = A.shape
+    lines = [f"{r} {n} 1 0 {int(l_batch)} 1", " ".join(str(int(m)) for m in M)]
+    lines.append(" ".join(f"{float(x.real).hex()} {float(x.imag).hex()}" for x in A.ravel()))
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0")
+    p = subprocess.run([str(EXE)], input="\n".join(lines) + "\n", capture_output=True, text=True, env=env,
+                       timeout=600)
+    if p.returncode != 0:
+        raise RuntimeError(f"walk_emu failed ({p.returncode}): {p.stderr[-2000:]}")
+    vals = p.stdout.split()
+    return np.array([complex(float.fromhex(vals[2 * i]), float.fromhex(vals[2 * i + 1])) for i in range(n)])

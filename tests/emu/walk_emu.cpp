@@ -8,10 +8,14 @@
 // every floating-point operation is written out (no contraction), the result
 // is expected to match the GPU bit for bit.
 //
-// stdin : n_rows n slots f32 l_batch / n_rows multiplicities / n_rows*n complex
-//         entries (re im, hex floats), row-major.  l_batch > 0 plans the item as a
-//         batched launch does (fixed unit length), 0 as a single launch.
-// stdout: re im rel_err_est kappa units   (hex floats, then an integer)
+// stdin : n_rows n slots f32 l_batch minors / n_rows multiplicities / n_rows*n
+//         complex entries (re im, hex floats), row-major.  l_batch > 0 plans the
+//         item as a batched launch does (fixed unit length), 0 as a single launch.
+//         minors = 1: the multiplicities sum to n - 1 and the n leave-one-column-
+//         out permanents are formed as the batched minors walk does (FP64).
+// stdout: re im rel_err_est kappa units   (hex floats, then an integer), or for
+//         minors n lines "re im" (permanent without column l, l = 0 .. n-1)
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -34,10 +38,10 @@ void run_unit(const WalkArgs& W, const PermDesc& d, uint32_t u, uint32_t lane, d
     }
 }
 
-int read_case(int& n_rows, int& n, long long& slots, int& f32, long long& l_batch, std::vector<int32_t>& M,
-              std::vector<double>& A)
+int read_case(int& n_rows, int& n, long long& slots, int& f32, long long& l_batch, int& minors,
+              std::vector<int32_t>& M, std::vector<double>& A)
 {
-    if (std::scanf("%d %d %lld %d %lld", &n_rows, &n, &slots, &f32, &l_batch) != 5) return 1;
+    if (std::scanf("%d %d %lld %d %lld %d", &n_rows, &n, &slots, &f32, &l_batch, &minors) != 6) return 1;
     M.resize((size_t)n_rows);
     for (int i = 0; i < n_rows; ++i)
         if (std::scanf("%d", &M[(size_t)i]) != 1) return 1;
@@ -197,17 +201,170 @@ int emulate(int n_rows, int n, long long slots, long long l_batch, const std::ve
     return 0;
 }
 
+// wavefront double-double butterfly of one value per lane (as the kernel's)
+void butterfly(ddv* sr, ddv* si)
+{
+    for (int off = 1; off < kWave; off <<= 1) {
+        ddv nr[kWave], ni[kWave];
+        for (int l = 0; l < kWave; ++l) {
+            nr[l] = dd_add(sr[l], sr[l ^ off]);
+            ni[l] = dd_add(si[l], si[l ^ off]);
+        }
+        for (int l = 0; l < kWave; ++l) {
+            sr[l] = nr[l];
+            si[l] = ni[l];
+        }
+    }
+}
+
+template <int KMIN, int KMAX>
+void run_minor_unit(const WalkArgs& W, const PermDesc& d, uint32_t u, uint32_t lane, double* r, double* i)
+{
+    if constexpr (KMIN <= KMAX) {
+        if (d.n == KMIN) walk_minors_unit<KMIN, minor_group(KMIN), double>(W, d, u, lane, r, i);
+        else run_minor_unit<KMIN + 1, KMAX>(W, d, u, lane, r, i);
+    }
+}
+
+// The batched minors path: targets in groups of minor_group(K), each group a
+// walk over its columns reordered (others first, targets last); per target the
+// unit partials are reduced as the finalize kernel does.
+int emulate_minors(int n_rows, int K, long long slots, long long l_batch, const std::vector<int32_t>& M,
+                   const std::vector<double>& A)
+{
+    HostPlan P;
+    std::string err;
+    PlanParams pp;
+    pp.l_batch = (uint64_t)l_batch;
+    int rc = build_plan(M.data(), n_rows, K - 1, (uint64_t)slots, pp, P, err);
+    if (rc) {
+        std::fprintf(stderr, "plan error %d: %s\n", rc, err.c_str());
+        return 2;
+    }
+    std::vector<double> out(2 * (size_t)K, 0.0);
+    if (K == 1) {
+        std::printf("%a %a\n", 1.0, 0.0);
+        return 0;
+    }
+    const int r = P.r;
+    const int G = minor_group(K);
+    const int groups = (K + G - 1) / G;
+    std::vector<double> binom((size_t)kBinomDim * kBinomDim);
+    for (int m = 0; m < kBinomDim; ++m)
+        for (int k = 0; k < kBinomDim; ++k) {
+            double v;
+            if (k > m) v = 0.0;
+            else if (k == 0 || k == m) v = 1.0;
+            else v = binom[(size_t)(m - 1) * kBinomDim + k - 1] + binom[(size_t)(m - 1) * kBinomDim + k];
+            binom[(size_t)m * kBinomDim + k] = v;
+        }
+    for (int gi = 0; gi < groups; ++gi) {
+        const int t0 = std::min(gi * G, K - G);
+        std::vector<int> cols;
+        for (int l = 0; l < K; ++l)
+            if (l < t0 || l >= t0 + G) cols.push_back(l);
+        for (int l = t0; l < t0 + G; ++l) cols.push_back(l);
+        std::vector<double> arena(2 * (size_t)r * (size_t)K * 3);
+        for (int k = 0; k < r; ++k)
+            for (int j = 0; j < K; ++j) {
+                const size_t src = 2 * ((size_t)P.src_row[(size_t)k] * K + (size_t)cols[(size_t)j]);
+                const double xr = A[src], xi = A[src + 1];
+                const size_t da = (size_t)k * K + j;
+                const size_t dp = (size_t)r * K + (size_t)(2 * k) * K + j;
+                const size_t dm = dp + (size_t)K;
+                arena[2 * da] = xr;
+                arena[2 * da + 1] = xi;
+                arena[2 * dp] = 2.0 * xr;
+                arena[2 * dp + 1] = 2.0 * xi;
+                arena[2 * dm] = -2.0 * xr;
+                arena[2 * dm + 1] = -2.0 * xi;
+            }
+        PermDesc d;
+        std::memset(&d, 0, sizeof d);
+        d.a2_off = (uint64_t)r * K;
+        d.tab = P.table->data();
+        d.units = P.units;
+        d.units_per_group = P.units_per_group;
+        d.span = P.span;
+        d.n = K;
+        d.r = r;
+        d.Q = P.Q;
+        d.lane_product = P.lane_product;
+        d.groups = P.groups;
+        d.scale = std::ldexp(1.0, 1 - (K - 1));
+        d.targets = (uint32_t)G;
+        WalkArgs W;
+        std::memset(&W, 0, sizeof W);
+        W.rowinfo = P.rows.data();
+        W.binom = binom.data();
+        W.a = arena.data();
+        W.a2 = arena.data();
+        emu_clear();
+        emu_register(P.rows.data(), sizeof(RowInfo) * P.rows.size());
+        emu_register(P.table->data(), sizeof(TabEntry) * P.table->size());
+        emu_register(binom.data(), sizeof(double) * binom.size());
+        emu_register(arena.data(), sizeof(double) * arena.size());
+        // partial (unit, target) -> (re hi, re lo, im hi, im lo)
+        std::vector<double> part((size_t)P.units * G * 4);
+        for (uint64_t u = 0; u < P.units; ++u) {
+            std::vector<double> lr((size_t)kWave * G), li((size_t)kWave * G);
+            for (uint32_t lane = 0; lane < (uint32_t)kWave; ++lane)
+                run_minor_unit<2, kMaxN>(W, d, (uint32_t)u, lane, lr.data() + (size_t)lane * G,
+                                         li.data() + (size_t)lane * G);
+            for (int t = 0; t < G; ++t) {
+                ddv sr[kWave], si[kWave];
+                for (int l = 0; l < kWave; ++l) {
+                    sr[l] = {lr[(size_t)l * G + t], 0.0};
+                    si[l] = {li[(size_t)l * G + t], 0.0};
+                }
+                butterfly(sr, si);
+                double* p = part.data() + ((size_t)u * G + t) * 4;
+                p[0] = sr[0].hi;
+                p[1] = sr[0].lo;
+                p[2] = si[0].hi;
+                p[3] = si[0].lo;
+            }
+        }
+        constexpr int T = 256;
+        for (int t = 0; t < G; ++t) {
+            if (t0 + t < gi * G) continue;  // owned by the previous group
+            std::vector<ddv> shr(T), shi(T);
+            for (int th = 0; th < T; ++th) {
+                ddv a = {0.0, 0.0}, b = {0.0, 0.0};
+                for (uint64_t u = (uint64_t)th; u < P.units; u += T) {
+                    const double* p = part.data() + ((size_t)u * G + t) * 4;
+                    a = dd_add(a, {p[0], p[1]});
+                    b = dd_add(b, {p[2], p[3]});
+                }
+                shr[(size_t)th] = a;
+                shi[(size_t)th] = b;
+            }
+            for (int sst = T / 2; sst > 0; sst >>= 1)
+                for (int th = 0; th < sst; ++th) {
+                    shr[(size_t)th] = dd_add(shr[(size_t)th], shr[(size_t)(th + sst)]);
+                    shi[(size_t)th] = dd_add(shi[(size_t)th], shi[(size_t)(th + sst)]);
+                }
+            const int l = t0 + t;
+            out[2 * (size_t)l] = (shr[0].hi + shr[0].lo) * d.scale;
+            out[2 * (size_t)l + 1] = (shi[0].hi + shi[0].lo) * d.scale;
+        }
+    }
+    for (int l = 0; l < K; ++l) std::printf("%a %a\n", out[2 * (size_t)l], out[2 * (size_t)l + 1]);
+    return 0;
+}
+
 }  // namespace
 
 int main()
 {
-    int n_rows = 0, n = 0, f32 = 0;
+    int n_rows = 0, n = 0, f32 = 0, minors = 0;
     long long slots = 0, l_batch = 0;
     std::vector<int32_t> M;
     std::vector<double> A;
-    if (read_case(n_rows, n, slots, f32, l_batch, M, A)) {
+    if (read_case(n_rows, n, slots, f32, l_batch, minors, M, A)) {
         std::fprintf(stderr, "bad input\n");
         return 2;
     }
+    if (minors) return emulate_minors(n_rows, n, slots, l_batch, M, A);
     return f32 ? emulate<float>(n_rows, n, slots, l_batch, M, A) : emulate<double>(n_rows, n, slots, l_batch, M, A);
 }

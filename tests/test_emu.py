@@ -79,3 +79,31 @@ def test_fp32_error_reported(oracle):
     e = rel(v, oracle.perm_generalized(A, M))
     assert e < 1e-3
     assert err > 1e-7
+
+
+def _minor_case(rng, K, modes):
+    """A random (A, M): rows from K-1 photons on `modes` modes, K columns."""
+    rows = rng.integers(0, modes, K - 1)
+    u = I.haar_from_rng(rng, max(modes, K))
+    kept, mult = I.bunch(rows, modes) if K > 1 else (np.array([0]), np.array([0], dtype=np.int32))
+    return np.ascontiguousarray(u[kept][:, :K]), mult
+
+
+@pytest.mark.parametrize("modes,Ks", [(60, (2, 3, 5, 9, 14, 17, 21)), (5, (22, 26, 31, 40))])
+def test_minors_walk_matches_oracle(oracle, modes, Ks):
+    """Every leave-one-column-out permanent of the joint walk (Laplace minors),
+    against the oracle's generalized permanent of the matrix without that column;
+    K spans one group (small K) and several groups, with a padded last group
+    (K = 21, 31, 40).  Heavy bunching (5 modes) keeps the large-K sums short but
+    makes them ill-conditioned (kappa up to ~1e7 at K = 40): the bar is 1e-10 or
+    the first-order bound kappa * (K + 64) * u, whichever is larger, with kappa
+    the oracle's sum of |addend| over |perm|."""
+    rng = np.random.default_rng(77 + modes)
+    for K in Ks:
+        A, M = _minor_case(rng, K, modes)
+        refs = [oracle.perm_generalized(np.delete(A, l, axis=1), M, with_abs=True) for l in range(K)]
+        for L in (64, 512):
+            got = emu.run_minors(A, M, L)
+            for l, (ref, absum) in enumerate(refs):
+                bar = max(TOL, absum / abs(ref) * (K + 64) * 2.0 ** -53)
+                assert rel(got[l], ref) <= bar, (K, l, M, L)

@@ -284,3 +284,69 @@ def test_gpu_matches_cpu_emulation_bitwise():
             gb = B.perm_batch([(A, M)])[0]
             eb, _, _, _ = emu.run(A, M, 1, l_batch=L)
             assert gb == eb, (n, gb, eb)
+
+
+def _minor_case(rng, K, modes):
+    rows = rng.integers(0, modes, K - 1)
+    u = I.haar_from_rng(rng, max(modes, K))
+    kept, mult = I.bunch(rows, modes)
+    return np.ascontiguousarray(u[kept][:, :K]), mult
+
+
+def test_minors_vs_oracle(oracle):
+    """perm_minors (one joint leave-one-column-out walk) against the oracle's
+    generalized permanent of every column-deleted matrix: K = 2..24 over 60
+    modes (one and two target groups) and K up to 36 with heavy bunching."""
+    rng = np.random.default_rng(303)
+    cases = [(K, 60) for K in (2, 3, 4, 7, 12, 16, 20, 24)] + [(K, 5) for K in (28, 33, 36)]
+    for K, modes in cases:
+        A, M = _minor_case(rng, K, modes)
+        say(f"case minors K={K} M={M.tolist()}")
+        got = B.perm_minors(A, M)
+        for l in range(K):
+            ref, absum = oracle.perm_generalized(np.delete(A, l, axis=1), M, with_abs=True)
+            bar = max(TOL, absum / abs(ref) * (K + 64) * 2.0 ** -53)
+            assert rel(got[l], ref) <= bar, (K, l, M.tolist())
+
+
+def test_minors_match_emulation_bitwise():
+    from tests.emu import emu
+    emu.build()
+    rng = np.random.default_rng(304)
+    for K, modes in ((9, 60), (21, 60), (31, 5), (40, 4)):
+        A, M = _minor_case(rng, K, modes)
+        say(f"case minors emulation K={K} M={M.tolist()}")
+        g = B.perm_minors(A, M)
+        e = emu.run_minors(A, M, B.batch_unit_length(K - 1))
+        assert np.array_equal(g, e), K
+
+
+def test_minors_laplace_identity():
+    """sum_l A[r, l] * minor_l equals the permanent of A with row r appended
+    (Laplace expansion along the appended row), for every candidate row r."""
+    rng = np.random.default_rng(305)
+    u = I.haar_from_rng(rng, 60)
+    K = 16
+    kept, M = I.bunch(rng.integers(0, 60, K - 1), 60)
+    A = np.ascontiguousarray(u[kept][:, :K])
+    minors = B.perm_minors(A, M)
+    for r in (0, 7, 59):
+        lap = np.dot(u[r, :K], minors)
+        rows = np.concatenate([kept, [r]])
+        uniq, inv = np.unique(rows, return_inverse=True)
+        Mr = np.bincount(inv, weights=np.concatenate([M, [1]]).astype(float)).astype(np.int32)
+        direct = B.perm_bbfg(np.ascontiguousarray(u[uniq][:, :K]), Mr)
+        assert rel(lap, direct) <= 1e-10, r
+
+
+def test_minors_errors():
+    A = np.ones((2, 3), dtype=np.complex128)
+    with pytest.raises(B.BBFGError):
+        B.perm_minors(A, [1, 2])   # sum must be n_cols - 1
+    with pytest.raises(B.BBFGError):
+        B.perm_minors(A, [-1, 3])
+    with pytest.raises(B.BBFGError):
+        B.perm_minors(np.ones((1, 49), dtype=np.complex128), [48])  # beyond BBFG_MAX_N
+    # the ones matrix: every minor is perm(J_2) = 2
+    assert np.allclose(B.perm_minors(A, [1, 1]), [2, 2, 2])
+    assert B.perm_minors(np.ones((1, 1), dtype=np.complex128), [0])[0] == 1
