@@ -1,9 +1,10 @@
-"""Benchmark of the generalized BB/FG permanent on one MI355X.
+"""Benchmark of the generalized BB/FG permanent and the sampler on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                    [--serve-jobs J] [--no-serving] [--no-batch]
 
-Workload (synthetic, seeded): the three single n = 30 generalized permanents
-of a 60 x 60 Haar unitary (seed 0):
+Headline workload (synthetic, seeded): the three single n = 30 generalized
+permanents of a 60 x 60 Haar unitary (seed 0):
   (a) 30 distinct rows, all M = 1            C' = 2^29
   (b) 10 distinct rows, each M = 3           C' = 3 * 4^9
   (c) 30 photons dropped at random on 60 modes (seed 2), zero-count rows removed
@@ -11,6 +12,15 @@ One step = one perm_bbfg call on each, inputs resident in device memory.
 value = algorithmic FP64 GFLOP/s over the step: C' * F(n) per permanent with
 F(n) = 8n - 4 flops per addend for M = 1 and 8n - 2 with multiplicities
 (column-sum update 2n, n - 1 complex products 6n - 6, accumulate 2, weight 2).
+
+Also reported on the same line:
+  batch   : 4096 uneven permanents (n uniform in [8, 24], photons on 60 modes)
+            in one persistent launch (graph replay), FP64 and FP32, with the
+            FP32 error against the FP64 results;
+  serving : Clifford & Clifford jobs (60-mode Haar unitary, n in {20,24,28,30}
+            photons, 16 samples each): one job at a time (bs_sample), all jobs
+            at once through the continuous-batching server (capacity), and
+            Poisson arrivals at fractions of that capacity (p50 / p99 latency).
 
 Prints ONE JSON line.  The dominant kernel's roofline uses the walk kernel's
 own device time, measured with HIP events on the stream it runs on.
@@ -30,6 +40,9 @@ sys.path.insert(0, ROOT)
 METRIC = "FP64 GFLOP/s (% of peak) for n=30 perm; BS samples/s + p99 latency, m=60"
 FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector: 256 CU x 128 flop/clk x 2.4 GHz
 CASES = ("a", "b", "c")
+# sources of the case-(a) walk kernel: its counter summary is void once they change
+KERNEL_SOURCES = ("paper_2309_07027_amd/csrc/walk_core.hpp", "paper_2309_07027_amd/csrc/walk.hip",
+                  "paper_2309_07027_amd/csrc/walk_device.hpp", "paper_2309_07027_amd/csrc/internal.hpp")
 
 
 def flops(n, M, cprime):
@@ -55,7 +68,7 @@ def measured_traffic():
     except (OSError, ValueError):
         return None
     h = hashlib.sha256()
-    for p in ("paper_2309_07027_amd/csrc/walk_core.hpp", "paper_2309_07027_amd/csrc/walk.hip"):
+    for p in KERNEL_SOURCES:
         with open(os.path.join(ROOT, p), "rb") as fh:
             h.update(fh.read())
     return rec["traffic_bytes_per_launch"] if h.hexdigest()[:16] == rec.get("kernel_source_hash") else None
@@ -77,6 +90,101 @@ def cpu_baseline(sample_terms: int):
                       f"double-double), {dt:.2f} s; GFLOP/s at the same 8n-4 flops per addend"}
 
 
+def batch_section(B, I, torch, np, reps: int):
+    """4096 uneven permanents in one launch: FP64 and FP32 (device-resident input)."""
+    items = I.c3(4096)
+    Ap, ao, nr, Mp, mo, nc = B.pack_batch(items)
+    Ad = torch.from_numpy(Ap).to("cuda")
+    addends = sum(cprime_of(M) for _, M in items)
+    fl = sum(flops(A.shape[1], M, cprime_of(M)) for A, M in items)
+    out = {"items": len(items), "n_range": [8, 24], "n_addends": addends, "flops": fl}
+    vals = {}
+    for prec, name in ((B.BBFG_FP64, "fp64"), (B.BBFG_FP32, "fp32")):
+        for _ in range(3):  # plans, tables, graph capture
+            B.perm_batch_packed(Ad, ao, nr, Mp, mo, nc, precision=prec)
+        walls, dev, graph = [], [], []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            v, err = B.perm_batch_packed(Ad, ao, nr, Mp, mo, nc, precision=prec, with_err=True)
+            walls.append(time.perf_counter() - t)
+            dev.append(B.batch_last_kernel_ms())
+            graph.append(B.batch_last_was_graph())
+        vals[name] = (v, err)
+        w = float(np.median(walls))
+        d = float(np.median(dev)) * 1e-3
+        out[name] = {"wall_ms": round(w * 1e3, 3), "graph_ms": round(d * 1e3, 3), "graph_replay": all(graph),
+                     "gflops_wall": round(fl / w / 1e9, 1), "gflops_graph": round(fl / d / 1e9, 1),
+                     "addends_per_s": float(f"{addends / w:.4g}"),
+                     "pct_fp64_peak_wall": round(100 * fl / w / 1e12 / FP64_PEAK_TFLOPS, 2)}
+    v64, e64 = vals["fp64"]
+    v32, e32 = vals["fp32"]
+    e = np.abs(v32 - v64) / np.abs(v64)
+    out["fp32"]["rel_err_vs_fp64"] = {"median": float(f"{np.median(e):.3g}"), "p99": float(f"{np.percentile(e, 99):.3g}"),
+                                      "max": float(f"{e.max():.3g}")}
+    out["fp32"]["rel_err_estimate_covers"] = float(np.mean(e <= e32 + 1e-15))
+    out["fp64"]["rel_err_estimate"] = {"median": float(f"{np.median(e64):.3g}"), "max": float(f"{e64.max():.3g}")}
+    return out
+
+
+def serving_section(B, I, np, n_jobs: int, fracs=(0.25, 0.5, 0.75, 0.9, 1.1)):
+    """Sampling jobs one at a time, all at once (capacity), then Poisson arrivals."""
+    jobs = [I.c4_job(j) for j in range(n_jobs)]
+    samples = sum(j[2] for j in jobs)
+    # warm-up: kernels and plans of every job size
+    for n in (20, 24, 28, 30):
+        U, occ, ns, loss, seed = next(j for j in jobs if int(j[1].sum()) == n)
+        B.bs_sample(U, occ, 2, loss, seed + 1)
+    solo, solo_t = [], []
+    t0 = time.perf_counter()
+    for U, occ, ns, loss, seed in jobs:
+        t = time.perf_counter()
+        solo.append(B.bs_sample(U, occ, ns, loss, seed))
+        solo_t.append(time.perf_counter() - t)
+    t_solo = time.perf_counter() - t0
+    out = {"jobs": n_jobs, "samples_per_job": int(jobs[0][2]), "m": 60,
+           "photons": sorted({int(j[1].sum()) for j in jobs}),
+           "one_at_a_time": {"samples_per_s": round(samples / t_solo, 1), "makespan_s": round(t_solo, 3),
+                             "job_s_p50": round(float(np.percentile(solo_t, 50)), 4),
+                             "job_s_p99": round(float(np.percentile(solo_t, 99)), 4)}}
+    with B.Server() as srv:
+        t0 = time.perf_counter()
+        ids = [srv.submit(U, occ, ns, loss, seed) for U, occ, ns, loss, seed in jobs]
+        srv.drain()
+        t_burst = time.perf_counter() - t0
+        res = [srv.poll(i) for i in ids]
+        st = srv.stats()
+    same = all(np.array_equal(r[0], s) for r, s in zip(res, solo))
+    mu = n_jobs / t_burst
+    out["all_at_once"] = {"samples_per_s": round(samples / t_burst, 1), "makespan_s": round(t_burst, 3),
+                          "speedup_vs_one_at_a_time": round(t_solo / t_burst, 3), "identical_to_alone": same,
+                          "max_active_jobs": int(st["max_active"]), "iterations": int(st["iterations"])}
+    sweep = []
+    for idx, f in enumerate(fracs):
+        rate = f * mu
+        arr = I.c4_arrivals(rate, n_jobs, idx)
+        with B.Server() as srv:
+            t0 = time.perf_counter()
+            ids = []
+            for j, (U, occ, ns, loss, seed) in enumerate(jobs):
+                wait = t0 + arr[j] - time.perf_counter()
+                if wait > 0:
+                    time.sleep(wait)
+                ids.append(srv.submit(U, occ, ns, loss, seed))
+            srv.drain()
+            t_end = time.perf_counter()
+            polled = [srv.poll(i) for i in ids]
+        lat = np.array([p[1] for p in polled])
+        same = same and all(np.array_equal(p[0], s) for p, s in zip(polled, solo))
+        sweep.append({"load": f, "offered_jobs_per_s": round(rate, 2),
+                      "samples_per_s": round(samples / (t_end - t0 - arr[0]), 1),
+                      "latency_s_p50": round(float(np.percentile(lat, 50)), 4),
+                      "latency_s_p99": round(float(np.percentile(lat, 99)), 4)})
+    out["poisson"] = sweep
+    out["identical_to_alone_all_runs"] = same
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,6 +192,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-log2", type=int, default=25)
+    ap.add_argument("--serve-jobs", type=int, default=128)
+    ap.add_argument("--batch-reps", type=int, default=10)
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run one plain device-to-device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
@@ -160,6 +272,15 @@ def main():
                       "n": 30, "m": 60, "permanents_per_step": 3},
            "pct_fp64_peak": round(100 * value / 1e3 / FP64_PEAK_TFLOPS, 2),
            "roofline": roofline, "cases": per_case}
+    if not args.no_batch:
+        out["batch"] = batch_section(B, I, torch, np, args.batch_reps)
+    if not args.no_serving:
+        sv = serving_section(B, I, np, args.serve_jobs)
+        out["serving"] = sv
+        near = min(sv["poisson"], key=lambda p: abs(p["load"] - 0.9))
+        out["bs_samples_per_s"] = sv["all_at_once"]["samples_per_s"]
+        out["bs_p99_latency_s"] = near["latency_s_p99"]
+        out["bs_p99_at_load"] = near["load"]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(1 << args.cpu_sample_log2)
     print(json.dumps(out), flush=True)
