@@ -196,6 +196,7 @@ def main():
     ap.add_argument("--batch-reps", type=int, default=10)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run one plain device-to-device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
@@ -272,6 +273,15 @@ def main():
                       "n": 30, "m": 60, "permanents_per_step": 3},
            "pct_fp64_peak": round(100 * value / 1e3 / FP64_PEAK_TFLOPS, 2),
            "roofline": roofline, "cases": per_case}
+    if not args.no_autotune and not (args.no_batch and args.no_serving):
+        # unit lengths of the batched launches, tuned on this device (untimed)
+        t0 = time.perf_counter()
+        tuned = {}
+        for prec, name, lo, hi in ((B.BBFG_FP64, "fp64", 8, 24), (B.BBFG_FP32, "fp32", 8, 24),
+                                   (B.BBFG_MINORS, "minors", 2, 29)):
+            B.autotune(lo, hi, precision=prec)
+            tuned[name] = {n: B.batch_unit_length(n, prec) for n in range(lo, hi + 1)}
+        out["autotune"] = {"seconds": round(time.perf_counter() - t0, 2), "unit_length": tuned}
     if not args.no_batch:
         out["batch"] = batch_section(B, I, torch, np, args.batch_reps)
     if not args.no_serving:

@@ -62,7 +62,9 @@ typedef enum {
     BBFG_ENOTFOUND = -6 /* unknown server job id */
 } bbfg_status;
 
-typedef enum { BBFG_FP64 = 0, BBFG_FP32 = 1 } bbfg_precision;
+/* BBFG_MINORS names the batched leave-one-column-out walks (FP64) in the
+ * autotuner calls only. */
+typedef enum { BBFG_FP64 = 0, BBFG_FP32 = 1, BBFG_MINORS = 2 } bbfg_precision;
 
 typedef struct {
     double re, im;
@@ -86,6 +88,14 @@ int bbfg_version(void);
 /* Initialise the library on the current HIP device (optional: every entry
  * point initialises lazily).  Errors: BBFG_EDEVICE. */
 int bbfg_init(void);
+
+/* Bounds of the per-device caches: plans (work splits, keyed by multiplicities
+ * and unit length) and Gray tables (16 bytes per entry, resident in device
+ * memory).  Past either bound the caches and the captured batch graphs are
+ * dropped, after the device has finished all queued work, and rebuilt on
+ * demand; results do not depend on the bounds.  0 restores a default (16384
+ * plans, 4 Mi entries = 64 MiB of tables). */
+int bbfg_set_cache_limits(uint64_t max_plans, uint64_t max_table_entries);
 
 /* Stream for the calling thread's subsequent calls (a hipStream_t, NULL = the
  * null stream).  The stream must stay valid while it is set. */
@@ -165,6 +175,8 @@ int perm_batch(int32_t batch, const bbfg_c128 *A_packed, const int64_t *A_offset
  *
  * FP64 with double-double reduction; no error estimate is formed (the
  * magnitude sums are not accumulated).  n_cols = 1 gives the empty permanent 1.
+ * The walk is split to fill the device (as perm_bbfg splits a lone permanent),
+ * so values may differ in the last bits from the minors the sampler forms.
  * Errors: EINVAL (NULL pointer, negative multiplicity, sum != n_cols - 1),
  * ERANGE (n_cols > BBFG_MAX_N), ENOMEM/EDEVICE.
  */
@@ -175,8 +187,8 @@ int perm_minors(const bbfg_c128 *A, int32_t n_rows, const int32_t *row_mult, int
 double perm_batch_last_kernel_ms(void);
 
 /* 1 when the last perm_batch on this thread replayed a captured hipGraph.  A
- * batch layout (shapes, multiplicities, buffer addresses) seen for the second
- * time is captured into a graph -- upload, gather, persistent walk, finalize,
+ * launch layout (metadata sizes, launch shapes, buffer addresses) seen for the
+ * second time is captured into a graph -- upload, gather, persistent walk, finalize,
  * download -- and replayed whenever it recurs. */
 int perm_batch_last_was_graph(void);
 
@@ -186,11 +198,16 @@ int perm_batch_last_was_graph(void);
  * function of the column count only, so an item's result does not depend on the
  * other items of the batch.  L is chosen by an autotuner that times synthetic
  * batches of n-photon permanents (photons at random on 60 modes) for
- * L in {64, ..., 4096} on the current device; untuned n use L = 512.
+ * L in {64, ..., 4096} on the current device; untuned n use L = 512.  The
+ * leave-one-column-out walks of the sampler (precision BBFG_MINORS; n = the
+ * size of the minors, n + 1 columns) are tuned separately: a unit of theirs
+ * ends with one reduction per target column.
  *
  * bbfg_autotune        tunes n in [n_lo, n_hi] for the given precision; when
  *                      cache_path is not NULL, writes every tuned entry to it as
  *                      text lines "precision n L".  Takes ~0.1-1 s per n.
+ *                      Samples drawn before and after tuning may differ in the
+ *                      last bits of their weights (the split changes).
  * bbfg_autotune_load   loads such a file (also done at initialisation when the
  *                      environment variable BBFG_AUTOTUNE_CACHE names one).
  * bbfg_batch_unit_length  the L currently used for n_cols columns.

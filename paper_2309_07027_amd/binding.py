@@ -23,6 +23,7 @@ BBFG_EBUSY = -5
 BBFG_ENOTFOUND = -6
 BBFG_FP64 = 0
 BBFG_FP32 = 1
+BBFG_MINORS = 2
 MAX_N = 48
 MAX_N_FP32 = 24
 
@@ -74,6 +75,7 @@ SIGNATURES = {
     "bbfg_version": (ctypes.c_int, []),
     "bbfg_init": (ctypes.c_int, []),
     "bbfg_set_stream": (ctypes.c_int, [_P]),
+    "bbfg_set_cache_limits": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_uint64]),
     "perm_bbfg": (ctypes.c_int, [_P, _I32, _PI32, _I32, _P, ctypes.POINTER(Info)]),
     "perm_batch": (ctypes.c_int, [_I32, _P, _PI64, _PI32, _PI32, _PI64, _PI32, _I32, _P, _PD]),
     "perm_minors": (ctypes.c_int, [_P, _I32, _PI32, _I32, _P]),
@@ -159,6 +161,11 @@ def _i64(x):
 
 def init():
     _check(lib().bbfg_init())
+
+
+def set_cache_limits(max_plans: int = 0, max_table_entries: int = 0):
+    """Bounds of the plan and Gray-table caches (0 = default)."""
+    _check(lib().bbfg_set_cache_limits(int(max_plans), int(max_table_entries)))
 
 
 def set_stream(stream=None):

@@ -7,10 +7,13 @@
 // tuned per n: a synthetic batch of n-photon permanents (photons placed at
 // random on 60 modes, as in the sampling workloads) is timed for each
 // candidate L and the fastest per addend is kept.  Untuned n use a default.
+// The leave-one-column-out walks of the sampler (kind BBFG_MINORS) end every
+// unit with one reduction per target column, so they are tuned on their own.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <deque>
 #include <vector>
 
 #include "runtime.hpp"
@@ -22,9 +25,10 @@ namespace {
 
 const uint64_t kCandidates[] = {64, 128, 256, 512, 1024, 2048, 4096};
 
-// Synthetic batch: `count` items of n photons on 60 modes; entries of modulus
-// 1/sqrt(n) with pseudo-random phases (the values do not affect the timing).
-void synthetic_batch(int n, int count, uint64_t seed, std::vector<double>& A, std::vector<int64_t>& aoff,
+// Synthetic batch: `count` items of n photons on 60 modes with `cols` columns
+// (n, or n + 1 for minors); entries of modulus 1/sqrt(n) with pseudo-random
+// phases (the values do not affect the timing).
+void synthetic_batch(int n, int cols, int count, uint64_t seed, std::vector<double>& A, std::vector<int64_t>& aoff,
                      std::vector<int32_t>& rows, std::vector<int32_t>& mult, std::vector<int64_t>& moff)
 {
     constexpr int kModes = 60;
@@ -44,7 +48,7 @@ void synthetic_batch(int n, int count, uint64_t seed, std::vector<double>& A, st
             if (cnt[k]) {
                 mult.push_back(cnt[k]);
                 ++r;
-                for (int j = 0; j < n; ++j) {
+                for (int j = 0; j < cols; ++j) {
                     const double ph = (double)(splitmix64_draw(seed, c++) >> 11) * 0x1.0p-53 * 6.283185307179586;
                     A.push_back(std::cos(ph) / std::sqrt((double)n));
                     A.push_back(std::sin(ph) / std::sqrt((double)n));
@@ -60,9 +64,12 @@ extern "C" {
 
 int bbfg_autotune(int32_t n_lo, int32_t n_hi, int32_t precision, const char* cache_path)
 {
-    const int f32 = precision == BBFG_FP32 ? 1 : 0;
-    if (precision != BBFG_FP64 && precision != BBFG_FP32) return set_error(BBFG_EINVAL, "bad precision");
-    const int max_n = f32 ? kMaxNF32 : kMaxN;
+    if (precision != BBFG_FP64 && precision != BBFG_FP32 && precision != BBFG_MINORS)
+        return set_error(BBFG_EINVAL, "bad precision");
+    const int kind = precision;
+    const bool minors = kind == BBFG_MINORS;
+    const int f32 = kind == BBFG_FP32 ? 1 : 0;
+    const int max_n = f32 ? kMaxNF32 : (minors ? kMaxN - 1 : kMaxN);
     if (n_lo < 1 || n_hi < n_lo || n_hi > max_n) return set_error(BBFG_ERANGE, "n range [%d, %d] invalid", n_lo, n_hi);
     Context* c = nullptr;
     BBFG_TRY(get_context(&c));
@@ -72,8 +79,10 @@ int bbfg_autotune(int32_t n_lo, int32_t n_hi, int32_t precision, const char* cac
         std::vector<double> A;
         std::vector<int64_t> aoff, moff;
         std::vector<int32_t> rows, mult;
-        const int count = 256;
-        synthetic_batch(n, count, 0x5eedULL * (uint64_t)n, A, aoff, rows, mult, moff);
+        // about 2^31 addends per timed launch (at most 256 items, at least 2)
+        const int count = (int)std::max<int64_t>(2, std::min<int64_t>(256, (int64_t(1) << 31) >> (n - 1)));
+        const int cols = minors ? n + 1 : n;
+        synthetic_batch(n, cols, count, 0x5eedULL * (uint64_t)n + (minors ? 7 : 0), A, aoff, rows, mult, moff);
         DevBuf dA;
         BBFG_TRY(dA.ensure(sizeof(double) * A.size()));
         BBFG_HIP(hipMemcpyAsync(dA.p, A.data(), sizeof(double) * A.size(), hipMemcpyHostToDevice, s));
@@ -81,19 +90,31 @@ int bbfg_autotune(int32_t n_lo, int32_t n_hi, int32_t precision, const char* cac
         double best_rate = -1.0;
         uint64_t best_L = kDefaultBatchUnit;
         for (uint64_t L : kCandidates) {
-            c->batch_L[std::make_pair(n, f32)] = L;
-            std::vector<PermItem> items((size_t)count);
-            uint64_t addends = 0;
+            c->batch_L[std::make_pair(n, kind)] = L;
+            std::vector<PermItem> items;
+            std::deque<std::vector<int32_t>> keep;
+            std::vector<uint32_t> slot((size_t)cols);
+            uint64_t addends = 0, nres = 0;
             for (int i = 0; i < count; ++i) {
-                PermItem& it = items[(size_t)i];
+                PermItem it;
                 it.src = dA.as<double>();
                 it.src_off = (uint64_t)aoff[(size_t)i];
-                it.ld = (uint32_t)n;
+                it.ld = (uint32_t)cols;
                 it.n_rows = rows[(size_t)i];
                 it.n = n;
                 it.mult = mult.data() + moff[(size_t)i];
-                BBFG_TRY(get_plan(*c, it.mult, it.n_rows, n, f32, PLAN_BATCH, &it.plan));
+                BBFG_TRY(get_plan(*c, it.mult, it.n_rows, n, kind, PLAN_BATCH, &it.plan));
                 addends += it.plan->n_addends;
+                if (minors) {
+                    keep.emplace_back((size_t)cols);
+                    for (int j = 0; j < cols; ++j) keep.back()[(size_t)j] = j;
+                    const int32_t* ident = keep.back().data();
+                    const size_t first = items.size();
+                    add_minor_items(it, ident, keep, items, nres, slot.data());
+                    for (size_t q = first; q < items.size(); ++q) nres += (uint64_t)items[q].targets;
+                } else {
+                    items.push_back(std::move(it));
+                }
             }
             double ms_best = 1e300;
             for (int rep = 0; rep < 3; ++rep) {
@@ -107,7 +128,7 @@ int bbfg_autotune(int32_t n_lo, int32_t n_hi, int32_t precision, const char* cac
                 best_L = L;
             }
         }
-        c->batch_L[std::make_pair(n, f32)] = best_L;
+        c->batch_L[std::make_pair(n, kind)] = best_L;
         dA.release();
     }
     if (cache_path) {
@@ -132,12 +153,14 @@ int bbfg_autotune_load(const char* cache_path)
 int bbfg_batch_unit_length(int32_t n_cols, int32_t precision, uint64_t* unit_length)
 {
     if (!unit_length) return set_error(BBFG_EINVAL, "unit_length is NULL");
-    const int f32 = precision == BBFG_FP32 ? 1 : 0;
-    if (n_cols < 1 || n_cols > (f32 ? kMaxNF32 : kMaxN)) return set_error(BBFG_ERANGE, "n_cols out of range");
+    if (precision != BBFG_FP64 && precision != BBFG_FP32 && precision != BBFG_MINORS)
+        return set_error(BBFG_EINVAL, "bad precision");
+    const int max_n = precision == BBFG_FP32 ? kMaxNF32 : (precision == BBFG_MINORS ? kMaxN - 1 : kMaxN);
+    if (n_cols < 1 || n_cols > max_n) return set_error(BBFG_ERANGE, "n_cols out of range");
     Context* c = nullptr;
     BBFG_TRY(get_context(&c));
     std::lock_guard<std::recursive_mutex> lk(c->mu);
-    *unit_length = batch_unit_length(*c, n_cols, f32);
+    *unit_length = batch_unit_length(*c, n_cols, precision);
     return BBFG_OK;
 }
 

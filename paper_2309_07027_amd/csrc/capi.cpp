@@ -73,6 +73,16 @@ int bbfg_init(void)
     return get_context(&c);
 }
 
+int bbfg_set_cache_limits(uint64_t max_plans, uint64_t max_table_entries)
+{
+    Context* c = nullptr;
+    BBFG_TRY(get_context(&c));
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    c->plan_cap = max_plans ? (size_t)max_plans : 16384;
+    c->table_entry_cap = max_table_entries ? (size_t)max_table_entries : (size_t(4) << 20);
+    return BBFG_OK;
+}
+
 int bbfg_set_stream(void* hip_stream)
 {
     set_current_stream(reinterpret_cast<hipStream_t>(hip_stream));
@@ -215,7 +225,9 @@ int perm_minors(const bbfg_c128* A, int32_t n_rows, const int32_t* row_mult, int
     proto.n_rows = n_rows;
     proto.n = n_cols - 1;
     proto.mult = row_mult;
-    BBFG_TRY(get_plan(*c, row_mult, n_rows, n_cols - 1, 0, PLAN_BATCH, &proto.plan));
+    // a lone call splits its sums to fill the device (the sampler's minors use
+    // the batch split, which depends on the item's shape only)
+    BBFG_TRY(get_plan(*c, row_mult, n_rows, n_cols - 1, 0, PLAN_SINGLE, &proto.plan));
     std::vector<int32_t> cols((size_t)n_cols);
     for (int32_t j = 0; j < n_cols; ++j) cols[(size_t)j] = j;
     std::deque<std::vector<int32_t>> keep;

@@ -194,7 +194,7 @@ int load_autotune_file(Context& c, const char* path)
     unsigned long long L = 0;
     int count = 0;
     while (std::fscanf(f, "%d %d %llu", &prec, &n, &L) == 3) {
-        if (n >= 1 && n <= kMaxN && L >= 1 && (prec == 0 || prec == 1)) {
+        if (n >= 1 && n <= kMaxN && L >= 1 && (prec == BBFG_FP64 || prec == BBFG_FP32 || prec == BBFG_MINORS)) {
             c.batch_L[std::make_pair(n, prec)] = (uint64_t)L;
             ++count;
         }
@@ -220,8 +220,8 @@ int get_plan(Context& c, const int32_t* mult, int n_rows, int n_cols, int f32, i
         return BBFG_OK;
     }
     uint64_t slots = 1;
-    if (n_cols >= 1) BBFG_TRY(walk_slots(c, n_cols, f32, &slots));
-    if (c.tables.entries > kTableEntryCap || c.plans.size() > kPlanCap) BBFG_TRY(flush_plans(c));
+    if (n_cols >= 1) BBFG_TRY(walk_slots(c, n_cols, f32 == 1 ? 1 : 0, &slots));
+    if (c.tables.entries > c.table_entry_cap || c.plans.size() >= c.plan_cap) BBFG_TRY(flush_plans(c));
     auto p = std::make_shared<HostPlan>();
     std::string err;
     const int rc = build_plan(mult, n_rows, n_cols, slots, pp, *p, err, &c.tables);
@@ -236,7 +236,7 @@ int device_table(Context& c, const HostPlan& p, const TabEntry** out)
     const void* host = p.table.get();
     auto it = c.dev_tables.find(host);
     if (it != c.dev_tables.end()) {
-        *out = it->second;
+        *out = it->second.second;
         return BBFG_OK;
     }
     const size_t bytes = sizeof(TabEntry) * p.table->size();
@@ -257,7 +257,7 @@ int device_table(Context& c, const HostPlan& p, const TabEntry** out)
     BBFG_HIP(hipMemcpyAsync(dst, p.table->data(), bytes, hipMemcpyHostToDevice, s));
     BBFG_HIP(hipStreamSynchronize(s));
     c.tab_used += need;
-    c.dev_tables.emplace(host, dst);
+    c.dev_tables.emplace(host, std::make_pair(p.table, dst));
     *out = dst;
     return BBFG_OK;
 }

@@ -88,18 +88,23 @@ struct Context {
     TableCache tables;
     std::vector<std::unique_ptr<DevBuf>> tab_chunks;
     size_t tab_chunk = 0, tab_used = 0;  // current chunk, bytes used in it
-    std::unordered_map<const void*, const TabEntry*> dev_tables;
+    // device copy of each host table; the entry holds the host table so that its
+    // address cannot be reused by another table while the entry exists
+    std::unordered_map<const void*, std::pair<TablePtr, const TabEntry*>> dev_tables;
+    size_t plan_cap = 16384;                   // cached plans before a flush
+    size_t table_entry_cap = size_t(4) << 20;  // cached table entries (16 B each) before a flush
     PlanParams params;
-    std::map<std::pair<int, int>, uint64_t> batch_L;  // (n, f32) -> tuned unit length
+    std::map<std::pair<int, int>, uint64_t> batch_L;  // (n, kind) -> tuned unit length
     // captured batch evaluations, keyed by layout (replayed on repeats)
     std::unordered_map<uint64_t, hipGraphExec_t> graphs;
     std::unordered_set<uint64_t> graph_seen;
     hipStream_t cstream = nullptr;  // capture stream
 };
 
-// Unit length used for n-column permanents in batched launches.
+// Unit length used for n-column permanents in batched launches; kind = 0
+// (FP64), 1 (FP32) or BBFG_MINORS (leave-one-column-out walks, n = minor size).
 constexpr uint64_t kDefaultBatchUnit = 512;
-uint64_t batch_unit_length(Context& c, int n, int f32);
+uint64_t batch_unit_length(Context& c, int n, int kind);
 
 // Plans for a single launch (units fill the device) or for batched launches
 // (fixed unit length: the split depends on the item's shape only).
@@ -115,14 +120,15 @@ int walk_slots(Context& c, int n, int f32, uint64_t* slots);
 // kKindMinors (leave-one-column-out walks).
 constexpr int kKindMinors = 2;
 int batch_waves(Context& c, int bucket, int kind, int* waves);
-int get_plan(Context& c, const int32_t* mult, int n_rows, int n_cols, int f32, int mode,
+// kind = 0 (FP64), 1 (FP32) or BBFG_MINORS: selects the tuned unit length of
+// PLAN_BATCH plans (plans of different kinds are cached separately).
+int get_plan(Context& c, const int32_t* mult, int n_rows, int n_cols, int kind, int mode,
              std::shared_ptr<const HostPlan>* out);
 // Device copy of a plan's Gray table (uploaded on first use, then resident).
 int device_table(Context& c, const HostPlan& p, const TabEntry** out);
-// Caches are bounded: past these sizes plans, tables and captured graphs are
-// dropped (after the device has drained) and rebuilt on demand.
-constexpr size_t kPlanCap = 16384;
-constexpr size_t kTableEntryCap = size_t(4) << 20;  // 64 MiB of table entries
+// Caches are bounded (Context::plan_cap, Context::table_entry_cap): past these
+// sizes plans, tables and captured graphs are dropped (after the device has
+// drained) and rebuilt on demand.
 constexpr size_t kTableChunkBytes = size_t(8) << 20;
 int flush_plans(Context& c);
 // Loads "precision n L" lines written by bbfg_autotune.

@@ -188,7 +188,7 @@ int cc_step(Context& c, std::vector<ActiveSample>& act, double* kernel_ms, uint6
                 mult.push_back(kv.second);
             }
             PermItem proto;
-            BBFG_TRY(get_plan(c, mult.data(), (int)mult.size(), k - 1, 0, PLAN_BATCH, &proto.plan));
+            BBFG_TRY(get_plan(c, mult.data(), (int)mult.size(), k - 1, BBFG_MINORS, PLAN_BATCH, &proto.plan));
             proto.src = J.A.as<double>();
             proto.src_off = 0;
             proto.ld = (uint32_t)J.n;

@@ -40,11 +40,12 @@ def run(A, M, slots: int, f32: bool = False, l_batch: int = 0):
     return complex(float.fromhex(re_), float.fromhex(im_)), float.fromhex(err), float.fromhex(kappa), int(units)
 
 
-def run_minors(A, M, l_batch: int):
-    """Emulated batched minors walk: [perm(A without column l, M) for each l]."""
+def run_minors(A, M, l_batch: int, slots: int = 1):
+    """Emulated minors walk: [perm(A without column l, M) for each l], planned with
+    unit length l_batch, or (l_batch = 0) to fill `slots` wavefront slots."""
     A = np.ascontiguousarray(np.asarray(A, dtype=np.complex128))
     r, n = A.shape
-    lines = [f"{r} {n} 1 0 {int(l_batch)} 1", " ".join(str(int(m)) for m in M)]
+    lines = [f"{r} {n} {int(slots)} 0 {int(l_batch)} 1", " ".join(str(int(m)) for m in M)]
     lines.append(" ".join(f"{float(x.real).hex()} {float(x.imag).hex()}" for x in A.ravel()))
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0")
     p = subprocess.run([str(EXE)], input="\n".join(lines) + "\n", capture_output=True, text=True, env=env,

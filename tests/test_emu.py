@@ -102,8 +102,8 @@ def test_minors_walk_matches_oracle(oracle, modes, Ks):
     for K in Ks:
         A, M = _minor_case(rng, K, modes)
         refs = [oracle.perm_generalized(np.delete(A, l, axis=1), M, with_abs=True) for l in range(K)]
-        for L in (64, 512):
-            got = emu.run_minors(A, M, L)
+        for L, slots in ((64, 1), (512, 1), (0, 2048)):
+            got = emu.run_minors(A, M, L, slots)
             for l, (ref, absum) in enumerate(refs):
                 bar = max(TOL, absum / abs(ref) * (K + 64) * 2.0 ** -53)
                 assert rel(got[l], ref) <= bar, (K, l, M, L)

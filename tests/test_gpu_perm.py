@@ -207,6 +207,11 @@ def test_batch_graph_replays_match_eager():
 def test_autotune_roundtrip(tmp_path):
     path = tmp_path / "tune.txt"
     B.autotune(8, 10, cache_path=str(path))
+    B.autotune(12, 13, precision=B.BBFG_MINORS, cache_path=str(path))
+    rows = [tuple(map(int, l.split())) for l in path.read_text().splitlines()]
+    assert {(0, n) for n in (8, 9, 10)} <= {(p, n) for p, n, _ in rows}
+    assert {(2, 12), (2, 13)} <= {(p, n) for p, n, _ in rows}
+    assert B.batch_unit_length(12, B.BBFG_MINORS) in (64, 128, 256, 512, 1024, 2048, 4096)
     lines = path.read_text().split()
     assert len(lines) >= 9
     for n in (8, 9, 10):
@@ -317,7 +322,8 @@ def test_minors_match_emulation_bitwise():
         A, M = _minor_case(rng, K, modes)
         say(f"case minors emulation K={K} M={M.tolist()}")
         g = B.perm_minors(A, M)
-        e = emu.run_minors(A, M, B.batch_unit_length(K - 1))
+        waves, ncu = B.walk_occupancy(K - 1)
+        e = emu.run_minors(A, M, 0, slots=waves * ncu)
         assert np.array_equal(g, e), K
 
 
@@ -350,3 +356,26 @@ def test_minors_errors():
     # the ones matrix: every minor is perm(J_2) = 2
     assert np.allclose(B.perm_minors(A, [1, 1]), [2, 2, 2])
     assert B.perm_minors(np.ones((1, 1), dtype=np.complex128), [0])[0] == 1
+
+
+def test_results_independent_of_cache_flushes():
+    """Plans, Gray tables and captured graphs are dropped and rebuilt when the
+    caches fill.  Tiny bounds force that many times per call, also while a batch
+    is being assembled, so host tables of earlier items are freed and their
+    addresses reused; no result may change in any bit."""
+    mats = [I.c3_item(i) for i in range(300)]
+    ref64 = B.perm_batch(mats)
+    ref32 = B.perm_batch(mats, precision=B.BBFG_FP32)
+    U = I.haar_from_rng(np.random.default_rng(71), 60)
+    occ = np.zeros(60, dtype=np.int32)
+    occ[:12] = 1
+    s_ref = B.bs_sample(U, occ, 8, 0.0, 99)
+    try:
+        B.set_cache_limits(8, 4096)
+        for rep in range(2):
+            say(f"case cache flushes rep {rep}")
+            assert np.array_equal(B.perm_batch(mats), ref64)
+            assert np.array_equal(B.perm_batch(mats, precision=B.BBFG_FP32), ref32)
+            assert np.array_equal(B.bs_sample(U, occ, 8, 0.0, 99), s_ref)
+    finally:
+        B.set_cache_limits(0, 0)
