@@ -1,7 +1,8 @@
 """Benchmark of the generalized BB/FG permanent and the sampler on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                    [--serve-jobs J] [--no-serving] [--no-batch]
+                    [--serve-jobs J] [--no-serving] [--no-batch] [--no-autotune]
+                    [--large-samples S]
 
 Headline workload (synthetic, seeded): the three single n = 30 generalized
 permanents of a 60 x 60 Haar unitary (seed 0):
@@ -20,7 +21,9 @@ Also reported on the same line:
   serving : Clifford & Clifford jobs (60-mode Haar unitary, n in {20,24,28,30}
             photons, 16 samples each): one job at a time (bs_sample), all jobs
             at once through the continuous-batching server (capacity), and
-            Poisson arrivals at fractions of that capacity (p50 / p99 latency).
+            Poisson arrivals at fractions of that capacity (p50 / p99 latency);
+  large   : 40-photon sampling on 60 modes, ideal and with transmission 0.5
+            (120 x 120 dilation), seconds per sample.
 
 Prints ONE JSON line.  The dominant kernel's roofline uses the walk kernel's
 own device time, measured with HIP events on the stream it runs on.
@@ -185,6 +188,22 @@ def serving_section(B, I, np, n_jobs: int, fracs=(0.25, 0.5, 0.75, 0.9, 1.1)):
     return out
 
 
+def large_sampling_section(B, I, samples: int):
+    """40 photons in the first 40 of 60 modes of Haar(5): ideal, and transmission
+    0.5 through the 120 x 120 dilation; seconds per sample."""
+    out = {"m": 60, "photons": 40, "samples": samples}
+    for lossy in (False, True):
+        U, occ, loss = I.c5(lossy)
+        B.bs_sample(U, occ, 1, loss, 1)  # plans and tables of the large steps
+        t = time.perf_counter()
+        s, info = B.bs_sample(U, occ, samples, loss, 5, with_info=True)
+        dt = time.perf_counter() - t
+        out["lossy_0.5" if lossy else "ideal"] = {"s_per_sample": round(dt / samples, 4),
+                                                   "walk_ms": round(info["kernel_ms"], 1),
+                                                   "photons_out": s.sum(axis=1).tolist()}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -197,6 +216,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--large-samples", type=int, default=2, help="samples per n = 40 run (0 = skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run one plain device-to-device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
@@ -291,6 +311,8 @@ def main():
         out["bs_samples_per_s"] = sv["all_at_once"]["samples_per_s"]
         out["bs_p99_latency_s"] = near["latency_s_p99"]
         out["bs_p99_at_load"] = near["load"]
+    if args.large_samples > 0:
+        out["large_sampling"] = large_sampling_section(B, I, args.large_samples)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(1 << args.cpu_sample_log2)
     print(json.dumps(out), flush=True)

@@ -151,3 +151,67 @@ def test_server_poll_busy_and_unknown():
         with pytest.raises(B.BBFGError) as e:
             srv.poll(jid)  # already collected
         assert e.value.code == B.BBFG_ENOTFOUND
+
+
+def _rows_of(counts):
+    rows = np.nonzero(counts)[0]
+    return rows, counts[rows].astype(np.int32)
+
+
+def test_c5_n40_ideal_and_lossy_sampling(oracle):
+    """Large sampling (40 photons in the first 40 of 60 modes of Haar(5)), ideal
+    and with transmission 0.5 through the 120 x 120 dilation.  The n = 40
+    permanents are beyond the oracle, so their parity rests on spot checks:
+    (i) the leave-one-column-out walk at 40 columns against independent single
+    permanents (other split, other column order) within their error estimates,
+    and the Laplace identity at 40 x 40; (ii) a minor of the same matrix and a
+    sampled row pattern that the oracle can evaluate."""
+    U, occ, _ = I.c5(False)
+    say("case c5 ideal")
+    s1 = B.bs_sample(U, occ, 1, 0.0, 5)
+    assert s1.sum() == 40 and (s1 >= 0).all()
+    assert np.array_equal(B.bs_sample(U, occ, 1, 0.0, 5), s1)
+    say("case c5 lossy")
+    U2, occ2, loss = I.c5(True)
+    s2 = B.bs_sample(U2, occ2, 1, loss, 6)
+    assert 0 <= s2.sum() <= 40 and (s2 >= 0).all()
+    with B.Server() as srv:
+        j = srv.submit(U2, occ2, 1, loss, 6)
+        srv.drain()
+        got, _ = srv.poll(j)
+    assert np.array_equal(got, s2)
+
+    # (i) minors of the sampled pattern with one photon removed, 40 columns
+    counts = s1[0].copy()
+    r_drop = int(np.nonzero(counts)[0][0])
+    counts[r_drop] -= 1
+    rows, M = _rows_of(counts)
+    A = np.ascontiguousarray(U[rows][:, :40])
+    say(f"case c5 minors K=40 rows={len(rows)}")
+    minors = B.perm_minors(A, M)
+    for l in (0, 13, 39):
+        v, info = B.perm_bbfg(np.ascontiguousarray(np.delete(A, l, axis=1)), M, with_info=True)
+        assert abs(minors[l] - v) <= 2 * max(1e-10, info["rel_err_est"]) * abs(v), l
+    for r in (r_drop, 59):
+        lap = np.dot(U[r, :40], minors)
+        full = counts.copy()
+        full[r] += 1
+        rr, Mr = _rows_of(full)
+        v, info = B.perm_bbfg(np.ascontiguousarray(U[rr][:, :40]), Mr, with_info=True)
+        assert abs(lap - v) <= 2 * max(1e-10, info["rel_err_est"]) * abs(v), r
+
+    # (ii) oracle spot check: 20 of the sampled photons, 21 columns
+    sub = np.zeros(60, dtype=np.int64)
+    left = 20
+    for r in np.nonzero(s1[0])[0]:
+        take = min(left, int(s1[0][r]))
+        sub[r] = take
+        left -= take
+        if left == 0:
+            break
+    rows, M = _rows_of(sub)
+    A = np.ascontiguousarray(U[rows][:, :21])
+    minors = B.perm_minors(A, M)
+    for l in (0, 20):
+        ref, absum = oracle.perm_generalized(np.delete(A, l, axis=1), M, with_abs=True)
+        assert abs(minors[l] - ref) <= max(1e-10, absum / abs(ref) * 84 * 2.0 ** -53) * abs(ref), l
