@@ -277,7 +277,9 @@ int bs_server_destroy(bbfg_server *srv);
 typedef struct {
     uint64_t jobs_submitted, jobs_done, iterations, samples_done;
     uint64_t max_active, max_queued;
-    double busy_s; /* worker time spent in device work */
+    double busy_s; /* worker time spent advancing samples (host preparation + device) */
+    double host_s; /* part of busy_s spent preparing steps on the host (plans, metadata, launches) */
+    double wait_s; /* part of busy_s spent waiting for the device to finish a step */
 } bbfg_server_stats;
 int bs_server_stats(bbfg_server *srv, bbfg_server_stats *out);
 

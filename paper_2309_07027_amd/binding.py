@@ -57,7 +57,8 @@ class PlanSummary(ctypes.Structure):
 class ServerStats(ctypes.Structure):
     _fields_ = [("jobs_submitted", ctypes.c_uint64), ("jobs_done", ctypes.c_uint64),
                 ("iterations", ctypes.c_uint64), ("samples_done", ctypes.c_uint64),
-                ("max_active", ctypes.c_uint64), ("max_queued", ctypes.c_uint64), ("busy_s", ctypes.c_double)]
+                ("max_active", ctypes.c_uint64), ("max_queued", ctypes.c_uint64), ("busy_s", ctypes.c_double),
+                ("host_s", ctypes.c_double), ("wait_s", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -78,6 +78,9 @@ constexpr int minor_group(int K)
     return (K + groups - 1) / groups;
 }
 
+constexpr uint32_t kUnitChunkLog2 = 6;
+constexpr uint32_t kUnitChunk = 1u << kUnitChunkLog2;
+
 // Sizes of the partial record of one unit: a complex double-double (4 doubles)
 // plus the sum of |addend| (1 double).
 constexpr int kPartialDoubles = 5;
@@ -109,10 +112,17 @@ struct WalkArgs {
     const float* a2f;
     const double* binom; // kBinomDim x kBinomDim
     double* partials;    // kPartialDoubles per unit slot
-    const uint32_t* unit_item;  // batch: item of each global unit
+    // batch: units are numbered item by item in "unit order"; position p of that
+    // order is item uorder[p], whose units start at ubase[p] (ubase has one more
+    // entry: the total).  uchunk[c] is the position of the item holding unit
+    // c * kUnitChunk (one more entry: the last position), which bounds the
+    // search for the item of a unit to the items of its chunk.
+    const uint32_t* ubase;
+    const uint32_t* uorder;
+    const uint32_t* uchunk;
     uint32_t* counter;          // batch: next unit
     uint32_t total_units;       // batch: number of units
-    uint32_t pad;
+    uint32_t nitem;             // batch: number of items
 };
 
 }  // namespace bbfg

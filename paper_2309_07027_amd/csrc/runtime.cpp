@@ -93,6 +93,22 @@ void PinnedBuf::release()
     cap = 0;
 }
 
+Workspace::~Workspace()
+{
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+    if (done) (void)hipEventDestroy(done);
+}
+
+int Workspace::init()
+{
+    if (!ev0) BBFG_HIP(hipEventCreate(&ev0));
+    if (!ev1) BBFG_HIP(hipEventCreate(&ev1));
+    if (!done) BBFG_HIP(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+    BBFG_TRY(counter.ensure(256));
+    return BBFG_OK;
+}
+
 bool is_device_ptr(const void* p)
 {
     if (!p) return false;
@@ -129,9 +145,7 @@ int get_context(Context** out)
     BBFG_HIP(hipMalloc(&c->binom, sizeof(double) * kBinomDim * kBinomDim));
     BBFG_HIP(launch_init_binom(c->binom, nullptr));
     BBFG_HIP(hipDeviceSynchronize());
-    BBFG_HIP(hipEventCreate(&c->ev0));
-    BBFG_HIP(hipEventCreate(&c->ev1));
-    BBFG_TRY(c->counter.ensure(256));
+    BBFG_TRY(c->ws.init());
     if (const char* path = std::getenv("BBFG_AUTOTUNE_CACHE")) {
         FILE* f = std::fopen(path, "r");
         if (f) {
@@ -231,15 +245,8 @@ int get_plan(Context& c, const int32_t* mult, int n_rows, int n_cols, int f32, i
     return BBFG_OK;
 }
 
-int device_table(Context& c, const HostPlan& p, const TabEntry** out)
+int table_reserve(Context& c, size_t bytes, TabEntry** out)
 {
-    const void* host = p.table.get();
-    auto it = c.dev_tables.find(host);
-    if (it != c.dev_tables.end()) {
-        *out = it->second.second;
-        return BBFG_OK;
-    }
-    const size_t bytes = sizeof(TabEntry) * p.table->size();
     const size_t need = (bytes + 255) / 256 * 256;
     if (c.tab_chunk < c.tab_chunks.size() && c.tab_used + need > c.tab_chunks[c.tab_chunk]->cap) {
         ++c.tab_chunk;
@@ -251,14 +258,8 @@ int device_table(Context& c, const HostPlan& p, const TabEntry** out)
         c.tab_chunks.push_back(std::move(b));
         c.tab_used = 0;
     }
-    TabEntry* dst = reinterpret_cast<TabEntry*>(c.tab_chunks[c.tab_chunk]->as<char>() + c.tab_used);
-    // synchronous: once listed, a table is complete for work on any stream
-    hipStream_t s = current_stream();
-    BBFG_HIP(hipMemcpyAsync(dst, p.table->data(), bytes, hipMemcpyHostToDevice, s));
-    BBFG_HIP(hipStreamSynchronize(s));
+    *out = reinterpret_cast<TabEntry*>(c.tab_chunks[c.tab_chunk]->as<char>() + c.tab_used);
     c.tab_used += need;
-    c.dev_tables.emplace(host, std::make_pair(p.table, dst));
-    *out = dst;
     return BBFG_OK;
 }
 
@@ -281,8 +282,8 @@ int flush_plans(Context& c)
 // ---------------------------------------------------------------------------
 // the permanent engine
 // ---------------------------------------------------------------------------
-int run_perms(Context& c, std::vector<PermItem>& items, int f32, bool single, double* out_host, double* diag_host,
-              RunResult* rr, bool sync, bool use_graph)
+int run_perms(Context& c, Workspace& w, std::vector<PermItem>& items, int f32, bool single, double* out_host,
+              double* diag_host, RunResult* rr, bool sync, bool use_graph)
 {
     const size_t nitem = items.size();
     if (nitem == 0) return BBFG_OK;
@@ -301,13 +302,42 @@ int run_perms(Context& c, std::vector<PermItem>& items, int f32, bool single, do
     // are resident on the device and shared between equal low radices)
     std::unordered_map<const HostPlan*, std::pair<size_t, const TabEntry*>> plan_slot;  // -> (rowinfo off, table)
     size_t n_rowinfo = 0, n_srcrow = 0, n_srccol = 0;
+    struct Upload {
+        const HostPlan* plan;
+        TabEntry* dst;
+        size_t bytes, off;
+    };
+    std::vector<Upload> uploads;        // tables this evaluation brings to the device
+    std::unordered_map<const void*, TabEntry*> uploading;  // their host tables -> pool space
+    std::vector<EventPtr> table_waits;  // uploads queued on other streams, maybe still running
+    size_t upload_bytes = 0;
     uint64_t a_elems = 0;
     int nmax = 0;
     for (auto& it : items) {
         const HostPlan* p = it.plan.get();
         if (plan_slot.find(p) == plan_slot.end()) {
+            auto te = c.dev_tables.find(p->table.get());
+            auto up = uploading.find(p->table.get());
             const TabEntry* dt = nullptr;
-            BBFG_TRY(device_table(c, *p, &dt));
+            if (te != c.dev_tables.end()) {
+                DevTable& e = te->second;
+                if (e.ready && e.stream != s) {
+                    if (hipEventQuery(e.ready.get()) == hipSuccess) e.ready.reset();
+                    else table_waits.push_back(e.ready);
+                }
+                dt = e.dev;
+            } else if (up != uploading.end()) {
+                dt = up->second;
+            } else {
+                // listed as resident only once its upload is queued (below)
+                const size_t bytes = sizeof(TabEntry) * p->table->size();
+                TabEntry* dst = nullptr;
+                BBFG_TRY(table_reserve(c, bytes, &dst));
+                uploads.push_back({p, dst, bytes, upload_bytes});
+                uploading[p->table.get()] = dst;
+                upload_bytes += (bytes + 255) / 256 * 256;
+                dt = dst;
+            }
             plan_slot[p] = {n_rowinfo, dt};
             n_rowinfo += (size_t)p->r;
         }
@@ -355,11 +385,15 @@ int run_perms(Context& c, std::vector<PermItem>& items, int f32, bool single, do
     const size_t off_prep = L.add(sizeof(PrepItem) * nitem);
     const size_t off_src = L.add(sizeof(uint32_t) * std::max<size_t>(1, n_srcrow));
     const size_t off_col = L.add(sizeof(uint32_t) * std::max<size_t>(1, n_srccol));
-    const size_t off_uitem = single ? 0 : L.add(sizeof(uint32_t) * (size_t)total_units);
+    const size_t nchunk = single ? 0 : (size_t)((total_units + kUnitChunk - 1) / kUnitChunk);
+    const size_t off_ubase = single ? 0 : L.add(sizeof(uint32_t) * (nitem + 1));
+    const size_t off_uorder = single ? 0 : L.add(sizeof(uint32_t) * nitem);
+    const size_t off_uchunk = single ? 0 : L.add(sizeof(uint32_t) * (nchunk + 1));
     const size_t off_ritem = L.add(sizeof(uint32_t) * (size_t)nres);
-    BBFG_TRY(c.hmeta.ensure(L.size));
-    BBFG_TRY(c.meta.ensure(L.size));
-    char* H = c.hmeta.as<char>();
+    const size_t off_tabs = L.add(std::max<size_t>(1, upload_bytes));
+    BBFG_TRY(w.hmeta.ensure(L.size));
+    BBFG_TRY(w.meta.ensure(L.size));
+    char* H = w.hmeta.as<char>();
     PermDesc* hd = reinterpret_cast<PermDesc*>(H + off_desc);
     RowInfo* hr = reinterpret_cast<RowInfo*>(H + off_row);
     PrepItem* hp = reinterpret_cast<PrepItem*>(H + off_prep);
@@ -368,6 +402,7 @@ int run_perms(Context& c, std::vector<PermItem>& items, int f32, bool single, do
     uint32_t* hri = reinterpret_cast<uint32_t*>(H + off_ritem);
     for (const auto& kv : plan_slot)
         std::memcpy(hr + kv.second.first, kv.first->rows.data(), sizeof(RowInfo) * (size_t)kv.first->r);
+    for (const Upload& u : uploads) std::memcpy(H + off_tabs + u.off, u.plan->table->data(), u.bytes);
     uint64_t a_cursor = 0;
     size_t s_cursor = 0, c_cursor = 0;
     for (size_t i = 0; i < nitem; ++i) {
@@ -417,32 +452,45 @@ int run_perms(Context& c, std::vector<PermItem>& items, int f32, bool single, do
         } else {
             q.srccol_off = kIdentityCols;
         }
-        if (!single) {
-            uint32_t* hu = reinterpret_cast<uint32_t*>(H + off_uitem);
-            for (uint64_t u = 0; u < p.units; ++u) hu[unit_base[i] + u] = (uint32_t)i;
+    }
+    if (!single) {
+        uint32_t* hb = reinterpret_cast<uint32_t*>(H + off_ubase);
+        uint32_t* ho = reinterpret_cast<uint32_t*>(H + off_uorder);
+        uint32_t* hk = reinterpret_cast<uint32_t*>(H + off_uchunk);
+        for (size_t oi = 0; oi < nitem; ++oi) {
+            const size_t i = order[oi];
+            const uint64_t b = unit_base[i], e = b + items[i].plan->units;
+            hb[oi] = (uint32_t)b;
+            ho[oi] = (uint32_t)i;
+            for (uint64_t c = (b + kUnitChunk - 1) / kUnitChunk; c * kUnitChunk < e; ++c) hk[c] = (uint32_t)oi;
         }
+        hb[nitem] = (uint32_t)total_units;
+        hk[nchunk] = (uint32_t)(nitem - 1);
     }
 
     // device buffers
-    if (f32) BBFG_TRY(c.arena_f.ensure(sizeof(float) * 2 * std::max<uint64_t>(1, a_elems)));
-    else BBFG_TRY(c.arena_d.ensure(sizeof(double) * 2 * std::max<uint64_t>(1, a_elems)));
-    BBFG_TRY(c.partials.ensure(sizeof(double) * kPartialDoubles * (size_t)total_parts));
-    BBFG_TRY(c.results.ensure(sizeof(double) * 4 * (size_t)nres));
-    BBFG_TRY(c.hres.ensure(sizeof(double) * 4 * (size_t)nres));
-    char* D = c.meta.as<char>();
+    if (f32) BBFG_TRY(w.arena_f.ensure(sizeof(float) * 2 * std::max<uint64_t>(1, a_elems)));
+    else BBFG_TRY(w.arena_d.ensure(sizeof(double) * 2 * std::max<uint64_t>(1, a_elems)));
+    BBFG_TRY(w.partials.ensure(sizeof(double) * kPartialDoubles * (size_t)total_parts));
+    BBFG_TRY(w.results.ensure(sizeof(double) * 4 * (size_t)nres));
+    BBFG_TRY(w.hres.ensure(sizeof(double) * 4 * (size_t)nres));
+    char* D = w.meta.as<char>();
 
     WalkArgs W;
     std::memset(&W, 0, sizeof W);
     W.descs = reinterpret_cast<const PermDesc*>(D + off_desc);
     W.rowinfo = reinterpret_cast<const RowInfo*>(D + off_row);
-    W.a = c.arena_d.as<double>();
-    W.a2 = c.arena_d.as<double>();
-    W.af = c.arena_f.as<float>();
-    W.a2f = c.arena_f.as<float>();
+    W.a = w.arena_d.as<double>();
+    W.a2 = w.arena_d.as<double>();
+    W.af = w.arena_f.as<float>();
+    W.a2f = w.arena_f.as<float>();
     W.binom = c.binom;
-    W.partials = c.partials.as<double>();
-    W.unit_item = single ? nullptr : reinterpret_cast<const uint32_t*>(D + off_uitem);
-    W.counter = c.counter.as<uint32_t>();
+    W.partials = w.partials.as<double>();
+    W.ubase = single ? nullptr : reinterpret_cast<const uint32_t*>(D + off_ubase);
+    W.uorder = single ? nullptr : reinterpret_cast<const uint32_t*>(D + off_uorder);
+    W.uchunk = single ? nullptr : reinterpret_cast<const uint32_t*>(D + off_uchunk);
+    W.nitem = (uint32_t)nitem;
+    W.counter = w.counter.as<uint32_t>();
     W.total_units = (uint32_t)total_units;
 
     int bucket = 0;
@@ -454,8 +502,8 @@ int run_perms(Context& c, std::vector<PermItem>& items, int f32, bool single, do
         BBFG_TRY(batch_waves(c, bucket, minors ? kKindMinors : f32, &waves));
         grid = std::min<uint64_t>((uint64_t)waves * (uint64_t)c.n_cu, total_units);
     }
-    double* R = c.results.as<double>();
-    double* HR = c.hres.as<double>();
+    double* R = w.results.as<double>();
+    double* HR = w.hres.as<double>();
 
     // Everything one evaluation puts on a stream (also what a graph captures):
     // metadata upload, gather, walk, finalize and, when results go back to the
@@ -464,19 +512,41 @@ int run_perms(Context& c, std::vector<PermItem>& items, int f32, bool single, do
         BBFG_HIP(hipMemcpyAsync(D, H, L.size, hipMemcpyHostToDevice, q));
         BBFG_HIP(launch_prep((uint32_t)nitem, q, reinterpret_cast<const PrepItem*>(D + off_prep),
                              reinterpret_cast<const uint32_t*>(D + off_src),
-                             reinterpret_cast<const uint32_t*>(D + off_col), c.arena_d.as<double>(),
-                             c.arena_d.as<double>(), c.arena_f.as<float>(), c.arena_f.as<float>()));
+                             reinterpret_cast<const uint32_t*>(D + off_col), w.arena_d.as<double>(),
+                             w.arena_d.as<double>(), w.arena_f.as<float>(), w.arena_f.as<float>()));
         if (!single) BBFG_HIP(launch_reset_counter(W.counter, q));
-        if (timed) BBFG_HIP(hipEventRecord(c.ev0, q));
+        if (timed) BBFG_HIP(hipEventRecord(w.ev0, q));
         if (single) BBFG_HIP(launch_walk_single(items[0].plan->n, f32, (uint32_t)total_units, q, W, 0u));
         else if (minors) BBFG_HIP(launch_walk_minors(bucket, (uint32_t)grid, q, W));
         else BBFG_HIP(launch_walk_batch(bucket, f32, (uint32_t)grid, q, W));
-        if (timed) BBFG_HIP(hipEventRecord(c.ev1, q));
+        if (timed) BBFG_HIP(hipEventRecord(w.ev1, q));
         BBFG_HIP(launch_finalize((uint32_t)nres, q, W.descs, reinterpret_cast<const uint32_t*>(D + off_ritem),
                                  W.partials, R, R + 2 * nres));
         if (sync) BBFG_HIP(hipMemcpyAsync(HR, R, sizeof(double) * 4 * nres, hipMemcpyDeviceToHost, q));
         return BBFG_OK;
     };
+
+    // Gray tables new to the device: copied from the pinned image in stream
+    // order (outside any captured graph), then an event that other streams wait
+    // for; tables uploaded on other streams and maybe not yet complete are waited
+    // for on the device
+    for (const EventPtr& e : table_waits) BBFG_HIP(hipStreamWaitEvent(s, e.get(), 0));
+    if (!uploads.empty()) {
+        hipEvent_t ev = nullptr;
+        BBFG_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        EventPtr ready(ev, [](hipEvent_t e) { (void)hipEventDestroy(e); });
+        for (const Upload& u : uploads)
+            BBFG_HIP(hipMemcpyAsync(u.dst, H + off_tabs + u.off, u.bytes, hipMemcpyHostToDevice, s));
+        BBFG_HIP(hipEventRecord(ev, s));
+        for (const Upload& u : uploads) {
+            DevTable e;
+            e.host = u.plan->table;
+            e.dev = u.dst;
+            e.ready = ready;
+            e.stream = s;
+            c.dev_tables[u.plan->table.get()] = std::move(e);
+        }
+    }
 
     bool launched = false;
     if (use_graph && sync) {
@@ -492,10 +562,11 @@ int run_perms(Context& c, std::vector<PermItem>& items, int f32, bool single, do
         };
         mix(&W, sizeof W);
         const uint64_t extra[] = {nitem, nres, (uint64_t)single, (uint64_t)minors, (uint64_t)f32, (uint64_t)bucket,
-                                  grid, L.size, off_desc, off_row, off_prep, off_src, off_col, off_uitem, off_ritem,
+                                  grid, L.size, off_desc, off_row, off_prep, off_src, off_col, off_ubase, off_uorder,
+                                  off_uchunk, off_ritem, off_tabs,
                                   (uint64_t)(uintptr_t)H, (uint64_t)(uintptr_t)D, (uint64_t)(uintptr_t)R,
-                                  (uint64_t)(uintptr_t)HR, (uint64_t)(uintptr_t)c.arena_d.p,
-                                  (uint64_t)(uintptr_t)c.arena_f.p};
+                                  (uint64_t)(uintptr_t)HR, (uint64_t)(uintptr_t)w.arena_d.p,
+                                  (uint64_t)(uintptr_t)w.arena_f.p};
         mix(extra, sizeof extra);
         auto git = c.graphs.find(key);
         if (git == c.graphs.end() && c.graph_seen.count(key)) {
@@ -518,9 +589,9 @@ int run_perms(Context& c, std::vector<PermItem>& items, int f32, bool single, do
             git = c.graphs.emplace(key, exec).first;
         }
         if (git != c.graphs.end()) {
-            BBFG_HIP(hipEventRecord(c.ev0, s));
+            BBFG_HIP(hipEventRecord(w.ev0, s));
             BBFG_HIP(hipGraphLaunch(git->second, s));
-            BBFG_HIP(hipEventRecord(c.ev1, s));
+            BBFG_HIP(hipEventRecord(w.ev1, s));
             launched = true;
             if (rr) rr->graph = true;
         } else {
@@ -536,7 +607,7 @@ int run_perms(Context& c, std::vector<PermItem>& items, int f32, bool single, do
     if (diag_host) std::memcpy(diag_host, HR + 2 * nres, sizeof(double) * 2 * nres);
     if (rr) {
         float ms = 0.f;
-        BBFG_HIP(hipEventElapsedTime(&ms, c.ev0, c.ev1));
+        BBFG_HIP(hipEventElapsedTime(&ms, w.ev0, w.ev1));
         rr->kernel_ms = ms;
         rr->units = total_units;
     }

@@ -9,6 +9,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <unordered_map>
 #include <unordered_set>
 #include <vector>
@@ -53,6 +54,10 @@ struct DevBuf {
 struct PinnedBuf {
     void* p = nullptr;
     size_t cap = 0;
+    PinnedBuf() = default;
+    PinnedBuf(const PinnedBuf&) = delete;
+    PinnedBuf& operator=(const PinnedBuf&) = delete;
+    ~PinnedBuf() { release(); }
     int ensure(size_t bytes);
     void release();
     template <typename T>
@@ -71,15 +76,45 @@ struct Layout {
     }
 };
 
+// ---- workspaces ----------------------------------------------------------------
+// Buffers of one evaluation in flight: the metadata image (pinned host and
+// device), gathered rows, unit partials, results, the sampler step's metadata,
+// the persistent-launch counter and timing events.  Grow-only and reused; a
+// workspace holds one evaluation at a time (the device context has one, the
+// sampling server two, so that it can prepare one step while another runs).
+struct Workspace {
+    DevBuf arena_d, arena_f, meta, partials, results, counter, cc_meta;
+    PinnedBuf hmeta, hres, cc_hmeta;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, done = nullptr;
+    Workspace() = default;
+    Workspace(const Workspace&) = delete;
+    Workspace& operator=(const Workspace&) = delete;
+    ~Workspace();
+    int init();  // events and counter (once, on the current device)
+};
+
+// A Gray table resident in device memory.  The entry holds the host table, so
+// that its address (the key) cannot be reused by another table while the entry
+// exists.  A table is uploaded in stream order by the first evaluation that
+// needs it (no host wait: a small copy queued behind a persistent walk would
+// wait for the whole walk); until the upload is known to be complete, `ready`
+// is the event recorded after it on `stream`, which other streams wait for.
+using EventPtr = std::shared_ptr<std::remove_pointer_t<hipEvent_t>>;
+struct DevTable {
+    TablePtr host;
+    const TabEntry* dev = nullptr;
+    EventPtr ready;
+    hipStream_t stream = nullptr;
+};
+
 // ---- per-device context -------------------------------------------------------
 struct Context {
     int device = -1;
     int n_cu = 0;
     std::recursive_mutex mu;
     double* binom = nullptr;
-    DevBuf arena_d, arena_f, meta, partials, results, staging, counter, cc_meta;
-    PinnedBuf hmeta, hres, cc_hmeta;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    DevBuf staging;
+    Workspace ws;
     std::map<std::pair<int, int>, int> occ_single;  // (n, f32) -> waves per CU
     std::map<std::pair<int, int>, int> occ_batch;   // (bucket, kind) -> waves per CU
     std::unordered_map<std::string, std::shared_ptr<const HostPlan>> plans;
@@ -88,9 +123,8 @@ struct Context {
     TableCache tables;
     std::vector<std::unique_ptr<DevBuf>> tab_chunks;
     size_t tab_chunk = 0, tab_used = 0;  // current chunk, bytes used in it
-    // device copy of each host table; the entry holds the host table so that its
-    // address cannot be reused by another table while the entry exists
-    std::unordered_map<const void*, std::pair<TablePtr, const TabEntry*>> dev_tables;
+    // device copy of each host table (keyed by the host table's address)
+    std::unordered_map<const void*, DevTable> dev_tables;
     size_t plan_cap = 16384;                   // cached plans before a flush
     size_t table_entry_cap = size_t(4) << 20;  // cached table entries (16 B each) before a flush
     PlanParams params;
@@ -124,8 +158,8 @@ int batch_waves(Context& c, int bucket, int kind, int* waves);
 // PLAN_BATCH plans (plans of different kinds are cached separately).
 int get_plan(Context& c, const int32_t* mult, int n_rows, int n_cols, int kind, int mode,
              std::shared_ptr<const HostPlan>* out);
-// Device copy of a plan's Gray table (uploaded on first use, then resident).
-int device_table(Context& c, const HostPlan& p, const TabEntry** out);
+// Pool space for a device table of `bytes` bytes (resident until a flush).
+int table_reserve(Context& c, size_t bytes, TabEntry** out);
 // Caches are bounded (Context::plan_cap, Context::table_entry_cap): past these
 // sizes plans, tables and captured graphs are dropped (after the device has
 // drained) and rebuilt on demand.
@@ -171,7 +205,14 @@ struct RunResult {
 // that reads c.results).  single = true uses the one-permanent launch.
 // use_graph = true captures a layout into a hipGraph the second time it is
 // seen and replays the graph from then on.
-int run_perms(Context& c, std::vector<PermItem>& items, int f32, bool single, double* out_host, double* diag_host,
-              RunResult* rr, bool sync = true, bool use_graph = false);
+// Runs in workspace w (the context's own by default); the results stay in
+// w.results.
+int run_perms(Context& c, Workspace& w, std::vector<PermItem>& items, int f32, bool single, double* out_host,
+              double* diag_host, RunResult* rr, bool sync = true, bool use_graph = false);
+inline int run_perms(Context& c, std::vector<PermItem>& items, int f32, bool single, double* out_host,
+                     double* diag_host, RunResult* rr, bool sync = true, bool use_graph = false)
+{
+    return run_perms(c, c.ws, items, f32, single, out_host, diag_host, rr, sync, use_graph);
+}
 
 }  // namespace bbfg

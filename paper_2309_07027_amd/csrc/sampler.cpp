@@ -17,6 +17,7 @@
 #include "sampler.hpp"
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <deque>
@@ -60,7 +61,7 @@ size_t cc_job_footprint(int m, int n, int n_samples, double loss)
 }
 
 int cc_job_init(Context& c, CCJob& job, const double* U, bool U_on_device, int m, const int32_t* occ, int n_samples,
-                double loss, uint64_t seed)
+                double loss, uint64_t seed, bool stage_pinned)
 {
     hipStream_t s = current_stream();
     job.m = m;
@@ -75,23 +76,30 @@ int cc_job_init(Context& c, CCJob& job, const double* U, bool U_on_device, int m
     job.samples.assign((size_t)n_samples, CCSample());
     job.out.assign((size_t)n_samples * (size_t)m, 0);
     job.started = job.finished = 0;
+    job.kernel_ms = 0.0;
+    job.n_addends = 0;
     if (job.n == 0) return BBFG_OK;
-    // device: [U (m x m) | cols (n int32)] staging, then A
-    const size_t ubytes = 16 * (size_t)m * (size_t)m;
-    BBFG_TRY(c.staging.ensure(ubytes + 4 * (size_t)job.n + 256));
-    char* st = c.staging.as<char>();
-    const double* Ud = U;
-    if (!U_on_device) {
-        BBFG_HIP(hipMemcpyAsync(st, U, ubytes, hipMemcpyHostToDevice, s));
-        Ud = reinterpret_cast<const double*>(st);
+    // device: [U (m x m), when on the host | cols (n int32)], then A
+    const size_t ubytes = U_on_device ? 0 : 16 * (size_t)m * (size_t)m;
+    const size_t ucap = (ubytes + 255) / 256 * 256;
+    BBFG_TRY(job.dev_in.ensure(ucap + 4 * (size_t)job.n));
+    char* in = job.dev_in.as<char>();
+    const double* Ud = U_on_device ? U : reinterpret_cast<const double*>(in);
+    int32_t* cols_d = reinterpret_cast<int32_t*>(in + ucap);
+    if (stage_pinned) {
+        BBFG_TRY(job.host_in.ensure(ucap + 4 * (size_t)job.n));
+        char* h = job.host_in.as<char>();
+        if (ubytes) std::memcpy(h, U, ubytes);
+        std::memcpy(h + ucap, job.cols.data(), 4 * (size_t)job.n);
+        BBFG_HIP(hipMemcpyAsync(in, h, ucap + 4 * (size_t)job.n, hipMemcpyHostToDevice, s));
+    } else {
+        if (ubytes) BBFG_HIP(hipMemcpyAsync(in, U, ubytes, hipMemcpyHostToDevice, s));
+        BBFG_HIP(hipMemcpyAsync(cols_d, job.cols.data(), 4 * (size_t)job.n, hipMemcpyHostToDevice, s));
     }
-    int32_t* cols_d = reinterpret_cast<int32_t*>(st + (ubytes + 255) / 256 * 256);
-    BBFG_HIP(hipMemcpyAsync(cols_d, job.cols.data(), 4 * (size_t)job.n, hipMemcpyHostToDevice, s));
     BBFG_TRY(job.A.ensure(16 * (size_t)job.rows * (size_t)job.n));
     const double eta = 1.0 - loss;
     BBFG_HIP(launch_build_job_matrix(Ud, m, cols_d, job.n, std::sqrt(eta), std::sqrt(1.0 - eta), loss > 0.0 ? 1 : 0,
                                      job.A.as<double>(), s));
-    BBFG_HIP(hipStreamSynchronize(s));  // the staging buffer is reused by later calls
     return BBFG_OK;
 }
 
@@ -150,15 +158,16 @@ void add_minor_items(const PermItem& proto, const int32_t* cols, std::deque<std:
     }
 }
 
-int cc_step(Context& c, std::vector<ActiveSample>& act, double* kernel_ms, uint64_t* addends)
+int cc_step_begin(Context& c, Workspace& w, std::vector<ActiveSample>& act, CCPending& p, uint64_t* addends)
 {
     hipStream_t s = current_stream();
+    p = CCPending();
     std::vector<PermItem> items;
     std::deque<std::vector<int32_t>> keep;  // multiplicities, row and column maps (stable addresses)
     std::vector<CCStep> steps;
     std::vector<int32_t> pis;
     std::vector<uint32_t> slots;            // result index of each minor
-    std::vector<size_t> act_of_step;
+    std::vector<size_t>& act_of_step = p.act_of_step;
     uint64_t nres = 0;
     for (size_t ai = 0; ai < act.size(); ++ai) {
         CCJob& J = *act[ai].job;
@@ -176,14 +185,20 @@ int cc_step(Context& c, std::vector<ActiveSample>& act, double* kernel_ms, uint6
         const uint64_t x = splitmix64_draw(S.key, (uint64_t)(J.n - 1 + (k - 1)));
         st.u = (double)(x >> 11) * 0x1.0p-53;
         if (k >= 2) {
-            // the k minors share the prefix rows: one joint walk over k columns
+            // the k minors share the prefix rows: one joint walk over k columns.
+            // Rows are listed by multiplicity (then mode), so the plan depends on
+            // the multiset of multiplicities only and is shared by many steps.
             std::map<int32_t, int32_t> cnt;
             for (int32_t r : S.prefix) cnt[r]++;
+            std::vector<std::pair<int32_t, int32_t>> rm(cnt.begin(), cnt.end());  // (mode, count)
+            std::sort(rm.begin(), rm.end(), [](const std::pair<int32_t, int32_t>& a, const std::pair<int32_t, int32_t>& b) {
+                return a.second != b.second ? a.second < b.second : a.first < b.first;
+            });
             keep.emplace_back();
             std::vector<int32_t>& rowmap = keep.back();
             keep.emplace_back();
             std::vector<int32_t>& mult = keep.back();
-            for (auto& kv : cnt) {
+            for (auto& kv : rm) {
                 rowmap.push_back(kv.first);
                 mult.push_back(kv.second);
             }
@@ -208,7 +223,8 @@ int cc_step(Context& c, std::vector<ActiveSample>& act, double* kernel_ms, uint6
     }
     if (steps.empty()) return BBFG_OK;
     RunResult rr;
-    if (!items.empty()) BBFG_TRY(run_perms(c, items, 0, false, nullptr, nullptr, &rr, false));
+    if (!items.empty()) BBFG_TRY(run_perms(c, w, items, 0, false, nullptr, nullptr, &rr, false));
+    p.has_items = !items.empty();
 
     Layout L;
     const size_t o_steps = L.add(sizeof(CCStep) * steps.size());
@@ -216,33 +232,57 @@ int cc_step(Context& c, std::vector<ActiveSample>& act, double* kernel_ms, uint6
     const size_t o_slot = L.add(sizeof(uint32_t) * std::max<size_t>(1, slots.size()));
     const size_t o_drawn = L.add(sizeof(int32_t) * steps.size());
     const size_t o_wsum = L.add(sizeof(double) * steps.size());
-    BBFG_TRY(c.cc_hmeta.ensure(L.size));
-    BBFG_TRY(c.cc_meta.ensure(L.size));
-    char* H = c.cc_hmeta.as<char>();
-    char* D = c.cc_meta.as<char>();
+    BBFG_TRY(w.cc_hmeta.ensure(L.size));
+    BBFG_TRY(w.cc_meta.ensure(L.size));
+    char* H = w.cc_hmeta.as<char>();
+    char* D = w.cc_meta.as<char>();
     std::memcpy(H + o_steps, steps.data(), sizeof(CCStep) * steps.size());
     std::memcpy(H + o_pi, pis.data(), sizeof(int32_t) * pis.size());
     if (!slots.empty()) std::memcpy(H + o_slot, slots.data(), sizeof(uint32_t) * slots.size());
     BBFG_HIP(hipMemcpyAsync(D, H, o_drawn, hipMemcpyHostToDevice, s));
     BBFG_HIP(launch_cc_weights((uint32_t)steps.size(), reinterpret_cast<const CCStep*>(D + o_steps),
                                reinterpret_cast<const int32_t*>(D + o_pi),
-                               reinterpret_cast<const uint32_t*>(D + o_slot), c.results.as<double>(),
+                               reinterpret_cast<const uint32_t*>(D + o_slot), w.results.as<double>(),
                                reinterpret_cast<int32_t*>(D + o_drawn), reinterpret_cast<double*>(D + o_wsum), s));
     BBFG_HIP(hipMemcpyAsync(H + o_drawn, D + o_drawn, L.size - o_drawn, hipMemcpyDeviceToHost, s));
-    BBFG_HIP(hipStreamSynchronize(s));
-    if (!items.empty() && kernel_ms) {
+    BBFG_HIP(hipEventRecord(w.done, s));
+    p.o_drawn = o_drawn;
+    p.queued = true;
+    return BBFG_OK;
+}
+
+int cc_step_end(Workspace& w, std::vector<ActiveSample>& act, CCPending& p, double* kernel_ms)
+{
+    if (!p.queued) return BBFG_OK;
+    p.queued = false;
+    BBFG_HIP(hipEventSynchronize(w.done));
+    if (p.has_items && kernel_ms) {
         float ms = 0.f;
-        BBFG_HIP(hipEventElapsedTime(&ms, c.ev0, c.ev1));
+        BBFG_HIP(hipEventElapsedTime(&ms, w.ev0, w.ev1));
         *kernel_ms += ms;
     }
-    const int32_t* drawn = reinterpret_cast<const int32_t*>(H + o_drawn);
-    for (size_t i = 0; i < steps.size(); ++i) {
-        ActiveSample& a = act[act_of_step[i]];
+    const int32_t* drawn = reinterpret_cast<const int32_t*>(w.cc_hmeta.as<char>() + p.o_drawn);
+    for (size_t i = 0; i < p.act_of_step.size(); ++i) {
+        ActiveSample& a = act[p.act_of_step[i]];
         CCSample& S = a.job->samples[(size_t)a.s];
         S.prefix.push_back(drawn[i]);
         S.k++;
         if (S.k > a.job->n) finish_sample(*a.job, a.s);
     }
+    return BBFG_OK;
+}
+
+int cc_step(Context& c, std::vector<ActiveSample>& act, double* kernel_ms, uint64_t* addends, double* host_s,
+            double* wait_s)
+{
+    using Clock = std::chrono::steady_clock;
+    const auto t0 = Clock::now();
+    CCPending p;
+    BBFG_TRY(cc_step_begin(c, c.ws, act, p, addends));
+    const auto t1 = Clock::now();
+    BBFG_TRY(cc_step_end(c.ws, act, p, kernel_ms));
+    if (host_s) *host_s += std::chrono::duration<double>(t1 - t0).count();
+    if (wait_s) *wait_s += std::chrono::duration<double>(Clock::now() - t1).count();
     return BBFG_OK;
 }
 

@@ -30,6 +30,8 @@ struct CCJob {
     uint64_t seed = 0;
     std::vector<int32_t> cols;  // input mode of each column (expanded occupation)
     DevBuf A;                   // rows x n complex, device
+    DevBuf dev_in;              // U (when given on the host) and cols, device
+    PinnedBuf host_in;          // pinned staging of dev_in (stage_pinned)
     std::vector<CCSample> samples;
     int started = 0;
     int finished = 0;
@@ -58,16 +60,40 @@ int cc_validate(const void* U, int m, const int32_t* occ, int n_samples, double 
 // Device bytes a job holds while active (its matrices plus a working-set share).
 size_t cc_job_footprint(int m, int n, int n_samples, double loss);
 
-// Copies U (host or device), builds the job matrix on the device.
+// Copies U (host or device) into the job's own device memory and queues the
+// build of the job matrix on the current stream (no synchronisation; a host U
+// must stay valid until the queued copy has run).  The job's device buffers
+// are grow-only: a CCJob can be reused for another job without new
+// allocations when it is large enough.
+// stage_pinned: the host-side inputs go through job.host_in (pinned), so the
+// copies are queued without waiting for work already on the stream.
 int cc_job_init(Context& c, CCJob& job, const double* U, bool U_on_device, int m, const int32_t* occ, int n_samples,
-                double loss, uint64_t seed);
+                double loss, uint64_t seed, bool stage_pinned = false);
 
 // Draws sample s's column order (Fisher-Yates with SplitMix64).
 void cc_start_sample(CCJob& job, int s);
 
-// Advances every listed sample by one step: all their minors in one batched
-// permanent launch, then one weights-and-draw launch.  Finished samples are
-// written to job.out and counted in job.finished.
-int cc_step(Context& c, std::vector<ActiveSample>& act, double* kernel_ms, uint64_t* addends);
+// One step of every listed sample, in two halves so that a caller can prepare
+// another step while this one runs:
+//   cc_step_begin queues (in workspace w, on the current stream) all the
+//     samples' minors in one batched leave-one-column-out launch, then one
+//     weights-and-draw launch and the download of the draws;
+//   cc_step_end waits for them and applies the draws.  Finished samples are
+//     written to job.out and counted in job.finished.
+// Between the two calls w, the samples and their jobs must stay untouched.
+struct CCPending {
+    std::vector<size_t> act_of_step;  // step i advances act[act_of_step[i]]
+    size_t o_drawn = 0;               // offset of the draws in w.cc_hmeta
+    bool has_items = false;           // a minors launch was queued (timed by w.ev0/ev1)
+    bool queued = false;
+};
+int cc_step_begin(Context& c, Workspace& w, std::vector<ActiveSample>& act, CCPending& p, uint64_t* addends);
+int cc_step_end(Workspace& w, std::vector<ActiveSample>& act, CCPending& p, double* kernel_ms);
+
+// Both halves back to back in the context's workspace.  host_s / wait_s
+// (nullable) accumulate the seconds spent preparing the step on the host and
+// waiting for the device.
+int cc_step(Context& c, std::vector<ActiveSample>& act, double* kernel_ms, uint64_t* addends,
+            double* host_s = nullptr, double* wait_s = nullptr);
 
 }  // namespace bbfg

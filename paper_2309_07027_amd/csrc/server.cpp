@@ -5,10 +5,12 @@
 // to keep many sampling jobs in flight and to evaluate the current step of all
 // of them together: a worker thread admits queued jobs while the device-memory
 // budget and the active-job limit allow, keeps every admitted job's matrix and
-// sample state resident, and in each iteration advances every unfinished
-// sample of every active job by one step with ONE batched permanent launch
-// (all minors, uneven sizes) and ONE weights-and-draw launch.  Jobs admitted
-// later simply join the next iteration.  A job's samples depend only on its
+// sample state resident, and advances the unfinished samples of every active
+// job step by step, each step ONE batched leave-one-column-out launch (all
+// minors, uneven sizes) and ONE weights-and-draw launch.  The samples are
+// split into two halves whose steps alternate on the device, so the host
+// prepares one half while the other runs.  Jobs admitted later simply join the
+// next step of each half.  A job's samples depend only on its
 // own arguments (the per-item work split and the reduction orders are fixed by
 // the item's shape), so they are bitwise identical to bs_sample's.
 #include <algorithm>
@@ -61,11 +63,16 @@ struct bbfg_server {
     uint64_t next_id = 1;
     std::deque<std::shared_ptr<SJob>> queue;
     std::vector<std::shared_ptr<SJob>> active;  // worker thread only
+    // sampler states of retired jobs, kept for reuse: freeing device memory
+    // would wait for the step in flight (worker thread only)
+    std::vector<std::unique_ptr<CCJob>> spare;
     std::unordered_map<uint64_t, std::shared_ptr<SJob>> jobs;
     size_t used = 0;
     size_t outstanding = 0;  // queued + active
     bbfg_server_stats st{};
     hipStream_t stream = nullptr;
+    int init_error = BBFG_OK;  // the worker could not set up its workspaces
+    std::string init_message;
 
     void run();
     void fail_active(int code, const std::string& msg);
@@ -73,6 +80,8 @@ struct bbfg_server {
 
 void bbfg_server::fail_active(int code, const std::string& msg)
 {
+    // nothing queued on the stream may still read the jobs' device memory
+    (void)hipStreamSynchronize(stream);
     std::lock_guard<std::mutex> lk(mu);
     for (auto& j : active) {
         j->state = 3;
@@ -87,16 +96,73 @@ void bbfg_server::fail_active(int code, const std::string& msg)
     cv_done.notify_all();
 }
 
+// The samples of every active job are split between two halves (sample s of a
+// job goes to half s % 2).  The halves alternate: while the device runs one
+// half's step, the worker applies the other half's draws, retires finished
+// jobs, admits new ones and queues that half's next step, so the device does
+// not wait for the host between steps.  Each half has its own workspace.
 void bbfg_server::run()
 {
     (void)hipSetDevice(device);
     set_current_stream(stream);
+    struct Half {
+        Workspace ws;
+        std::vector<ActiveSample> act;
+        CCPending pend;
+    };
+    Half half[2];
+    for (Half& h : half) {
+        const int rc = h.ws.init();
+        if (rc != BBFG_OK) {
+            std::lock_guard<std::mutex> lk(mu);
+            init_error = rc;
+            init_message = last_error();
+        }
+    }
+    int which = 0;
     for (;;) {
+        Half& h = half[which];
+        const auto t0 = Clock::now();
+        int rc = BBFG_OK;
+        // 1. the draws of this half's step in flight
+        if (h.pend.queued) {
+            rc = cc_step_end(h.ws, h.act, h.pend, nullptr);
+            const double dt = std::chrono::duration<double>(Clock::now() - t0).count();
+            std::lock_guard<std::mutex> lk(mu);
+            st.wait_s += dt;
+            st.busy_s += dt;
+            st.iterations++;
+        }
+        if (rc != BBFG_OK) {
+            half[0].pend.queued = half[1].pend.queued = false;
+            fail_active(rc, last_error());
+            continue;
+        }
+        // 2. retire finished jobs, admit queued ones (or sleep when idle)
         std::vector<std::shared_ptr<SJob>> admitted;
         {
             std::unique_lock<std::mutex> lk(mu);
+            std::vector<std::shared_ptr<SJob>> keep;
+            for (auto& j : active) {
+                const bool done = j->cc->n == 0 || j->cc->finished == j->n_samples;
+                if (!done) {
+                    keep.push_back(j);
+                    continue;
+                }
+                j->out = j->cc->out;
+                spare.push_back(std::move(j->cc));
+                j->state = 2;
+                j->t_done = Clock::now();
+                used -= j->footprint;
+                --outstanding;
+                st.jobs_done++;
+                st.samples_done += (uint64_t)j->n_samples;
+            }
+            if (keep.size() != active.size()) cv_done.notify_all();
+            active.swap(keep);
             for (;;) {
-                while (!stop && !queue.empty() && (int)(active.size() + admitted.size()) < max_active) {
+                while (!stop && init_error == BBFG_OK && !queue.empty() &&
+                       (int)(active.size() + admitted.size()) < max_active) {
                     auto& j = queue.front();
                     const bool empty = active.empty() && admitted.empty();
                     if (!empty && used + j->footprint > budget) break;  // wait for memory to free up
@@ -105,61 +171,70 @@ void bbfg_server::run()
                     admitted.push_back(j);
                     queue.pop_front();
                 }
-                if (!active.empty() || !admitted.empty() || stop) break;  // (stop: queued jobs never start)
+                const bool other_busy = half[which ^ 1].pend.queued;
+                if (!active.empty() || !admitted.empty() || other_busy || stop) break;
+                if (init_error != BBFG_OK && !queue.empty()) break;
                 cv_work.wait(lk);
             }
-            if (stop && active.empty() && admitted.empty()) return;
+            if (stop && active.empty() && admitted.empty() && !half[0].pend.queued && !half[1].pend.queued) return;
             const uint64_t na = active.size() + admitted.size();
             if (na > st.max_active) st.max_active = na;
+            if (init_error != BBFG_OK) {
+                // the worker cannot run steps: fail what is queued
+                for (auto& j : queue) {
+                    j->state = 3;
+                    j->err_code = init_error;
+                    j->err = init_message;
+                    j->t_done = Clock::now();
+                    --outstanding;
+                }
+                queue.clear();
+                cv_done.notify_all();
+            }
         }
-        const auto t0 = Clock::now();
-        int rc = BBFG_OK;
+        // 3. set up admitted jobs, queue this half's next step
+        const auto t1 = Clock::now();
         {
             std::lock_guard<std::recursive_mutex> clk(ctx->mu);
             for (auto& j : admitted) {
-                j->cc = std::make_unique<CCJob>();
+                if (!spare.empty()) {
+                    j->cc = std::move(spare.back());
+                    spare.pop_back();
+                } else {
+                    j->cc = std::make_unique<CCJob>();
+                }
                 rc = cc_job_init(*ctx, *j->cc, j->U.data(), false, j->m, j->occ.data(), j->n_samples, j->loss,
-                                 j->seed);
+                                 j->seed, true);
                 if (rc != BBFG_OK) break;
                 for (int s = 0; s < j->n_samples; ++s) cc_start_sample(*j->cc, s);
+                std::lock_guard<std::mutex> lk(mu);
                 active.push_back(j);
             }
             if (rc == BBFG_OK) {
-                std::vector<ActiveSample> act;
+                h.act.clear();
                 for (auto& j : active)
-                    for (int s = 0; s < j->n_samples; ++s)
-                        if (j->cc->n > 0 && j->cc->samples[(size_t)s].k <= j->cc->n) act.push_back({j->cc.get(), s});
-                if (!act.empty()) rc = cc_step(*ctx, act, nullptr, nullptr);
+                    for (int s = which; s < j->n_samples; s += 2)
+                        if (j->cc->n > 0 && j->cc->samples[(size_t)s].k <= j->cc->n) h.act.push_back({j->cc.get(), s});
+                if (!h.act.empty()) rc = cc_step_begin(*ctx, h.ws, h.act, h.pend, nullptr);
             }
         }
         if (rc != BBFG_OK) {
-            for (auto& j : admitted)
-                if (!j->cc || std::find(active.begin(), active.end(), j) == active.end()) active.push_back(j);
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                for (auto& j : admitted)
+                    if (std::find(active.begin(), active.end(), j) == active.end()) active.push_back(j);
+            }
+            half[0].pend.queued = half[1].pend.queued = false;
             fail_active(rc, last_error());
             continue;
         }
-        const double busy = std::chrono::duration<double>(Clock::now() - t0).count();
-        std::lock_guard<std::mutex> lk(mu);
-        st.busy_s += busy;
-        st.iterations++;
-        std::vector<std::shared_ptr<SJob>> keep;
-        for (auto& j : active) {
-            const bool done = j->cc->n == 0 || j->cc->finished == j->n_samples;
-            if (!done) {
-                keep.push_back(j);
-                continue;
-            }
-            j->out = j->cc->out;
-            j->cc.reset();
-            j->state = 2;
-            j->t_done = Clock::now();
-            used -= j->footprint;
-            --outstanding;
-            st.jobs_done++;
-            st.samples_done += (uint64_t)j->n_samples;
+        {
+            const double dt = std::chrono::duration<double>(Clock::now() - t1).count();
+            std::lock_guard<std::mutex> lk(mu);
+            st.host_s += dt;
+            st.busy_s += dt;
         }
-        active.swap(keep);
-        cv_done.notify_all();
+        which ^= 1;
     }
 }
 

@@ -10,6 +10,23 @@
 
 namespace bbfg {
 
+// Item of global unit u in a batched launch: a scalar binary search over the
+// first units of the items of u's chunk (invariant ubase[lo] <= u < ubase[hi]).
+__device__ __forceinline__ uint32_t item_of_unit(const WalkArgs& A, uint32_t u)
+{
+    kptr<uint32_t> base = kconst(A.ubase);
+    kptr<uint32_t> chunk = kconst(A.uchunk);
+    const uint32_t c = u >> kUnitChunkLog2;
+    uint32_t lo = chunk[c];
+    uint32_t hi = chunk[c + 1] + 1;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (base[mid] <= u) lo = mid;
+        else hi = mid;
+    }
+    return uniform_u32(kconst(A.uorder)[lo]);
+}
+
 // Wavefront sum of the per-lane results in double-double (the butterfly leaves
 // the same bits in every lane), then lane 0 stores the unit's partial record.
 __device__ __forceinline__ void store_partial(double* partials, uint64_t slot, double r, double i, double a)

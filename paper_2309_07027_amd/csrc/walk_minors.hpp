@@ -49,7 +49,7 @@ __global__ __launch_bounds__(kWave) void walk_minors_batch_kernel(WalkArgs A)
         const uint32_t u = __builtin_amdgcn_readfirstlane(next_unit);
         __syncthreads();
         if (u >= A.total_units) break;
-        const uint32_t item = __builtin_amdgcn_readfirstlane(A.unit_item[u]);
+        const uint32_t item = item_of_unit(A, u);
         const PermDesc d = A.descs[item];
         dispatch_minors<2, KMAX>(A, d, u - (uint32_t)d.unit_base);
     }
