@@ -160,6 +160,26 @@ int perm_batch(int32_t batch, const bbfg_c128 *A_packed, const int64_t *A_offset
                const int32_t *n_cols, int32_t precision, bbfg_c128 *out, double *rel_err_est);
 
 /*
+ * perm_bbfg_cols -- the generalized permanent with row AND column
+ * multiplicities (Eq. bbfgrepeated): the permanent of the n x n matrix in which
+ * row i of A appears row_mult[i] times and column j col_mult[j] times,
+ *   2^{1-n} sum_Delta w(Delta) prod_j (column sum j)^{N_j}.
+ * A repeated column's sum is formed and updated once per addend and enters the
+ * product N_j times, instead of N_j identical sums of the expanded matrix.
+ *
+ *   A         n_rows x n_cols complex (distinct columns), row-major, host or device.
+ *   row_mult  n_rows int32 (host), >= 0.
+ *   col_mult  n_cols int32 (host), >= 0; sum(col_mult) = sum(row_mult) = n
+ *             <= BBFG_MAX_N.  Zero rows and columns are dropped.
+ *   out, info as perm_bbfg (FP64, double-double reduction, error estimate).
+ *
+ * n = 0 gives 1.  Errors: EINVAL (NULL pointer, negative multiplicity, sums
+ * differ), ERANGE (n > BBFG_MAX_N), ENOMEM/EDEVICE.
+ */
+int perm_bbfg_cols(const bbfg_c128 *A, int32_t n_rows, const int32_t *row_mult, int32_t n_cols,
+                   const int32_t *col_mult, bbfg_c128 *out, bbfg_info *info);
+
+/*
  * perm_minors -- every leave-one-column-out permanent of one matrix, from one
  * joint walk: the minors of the Laplace expansion that the Clifford & Clifford
  * step of Sec. 4 needs for all candidate output modes at once.  All minors

@@ -80,6 +80,7 @@ SIGNATURES = {
     "perm_bbfg": (ctypes.c_int, [_P, _I32, _PI32, _I32, _P, ctypes.POINTER(Info)]),
     "perm_batch": (ctypes.c_int, [_I32, _P, _PI64, _PI32, _PI32, _PI64, _PI32, _I32, _P, _PD]),
     "perm_minors": (ctypes.c_int, [_P, _I32, _PI32, _I32, _P]),
+    "perm_bbfg_cols": (ctypes.c_int, [_P, _I32, _PI32, _I32, _PI32, _P, ctypes.POINTER(Info)]),
     "perm_batch_last_kernel_ms": (ctypes.c_double, []),
     "perm_batch_last_was_graph": (ctypes.c_int, []),
     "bs_sample": (ctypes.c_int, [_P, _I32, _PI32, _I32, ctypes.c_double, ctypes.c_uint64, _PI32,
@@ -234,6 +235,20 @@ def perm_batch_packed(A_packed, a_off, n_rows, M_packed, m_off, n_cols, precisio
 def perm_batch(mats, precision: int = BBFG_FP64, with_err: bool = False):
     """Permanents of [(A, M), ...] (host matrices) in one batched launch."""
     return perm_batch_packed(*pack_batch(mats), precision=precision, with_err=with_err)
+
+
+def perm_bbfg_cols(A, row_mult, col_mult, with_info: bool = False):
+    """Permanent with row and column multiplicities (Eq. bbfgrepeated): A holds the
+    distinct rows and columns; sum(row_mult) == sum(col_mult)."""
+    ptr, keep, shape = _cmat_ptr(A)
+    r, c = shape
+    m, pm = _i32(row_mult)
+    cm, pc = _i32(col_mult)
+    out = np.zeros(1, dtype=np.complex128)
+    info = Info()
+    _check(lib().perm_bbfg_cols(ptr, r, pm, c, pc, ctypes.c_void_p(out.ctypes.data), ctypes.byref(info)))
+    del keep
+    return (complex(out[0]), info.as_dict()) if with_info else complex(out[0])
 
 
 def perm_minors(A, M):

@@ -247,6 +247,65 @@ int perm_minors(const bbfg_c128* A, int32_t n_rows, const int32_t* row_mult, int
     return write_results(out, res.data(), (size_t)n_cols);
 }
 
+int perm_bbfg_cols(const bbfg_c128* A, int32_t n_rows, const int32_t* row_mult, int32_t n_cols, const int32_t* col_mult,
+                   bbfg_c128* out, bbfg_info* info)
+{
+    if (!out) return set_error(BBFG_EINVAL, "out is NULL");
+    if (n_cols < 0) return set_error(BBFG_EINVAL, "n_cols = %d < 0", n_cols);
+    if (n_cols > 0 && !col_mult) return set_error(BBFG_EINVAL, "col_mult is NULL");
+    int64_t n = 0;
+    std::vector<int32_t> keep_cols;
+    std::vector<uint8_t> exps;
+    for (int32_t j = 0; j < n_cols; ++j) {
+        if (col_mult[j] < 0) return set_error(BBFG_EINVAL, "col_mult[%d] = %d < 0", j, col_mult[j]);
+        n += col_mult[j];
+        if (n > kMaxN) return set_error(BBFG_ERANGE, "sum(col_mult) exceeds the maximum %d", kMaxN);
+        if (col_mult[j] > 0) {
+            keep_cols.push_back(j);
+            exps.push_back((uint8_t)col_mult[j]);
+        }
+    }
+    BBFG_TRY(validate_shape(row_mult, n_rows, (int32_t)n, kMaxN));
+    if (info) std::memset(info, 0, sizeof *info);
+    if (n == 0) {
+        const double one[2] = {1.0, 0.0};
+        if (info) {
+            info->kappa = 1.0;
+            info->n_addends = 1;
+        }
+        return write_results(out, one, 1);
+    }
+    if (!A) return set_error(BBFG_EINVAL, "A is NULL");
+    Context* c = nullptr;
+    BBFG_TRY(get_context(&c));
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    const double* Ad = nullptr;
+    BBFG_TRY(device_view(*c, A, (uint64_t)n_rows * (uint64_t)n_cols, &Ad));
+    std::vector<PermItem> items(1);
+    PermItem& it = items[0];
+    it.src = Ad;
+    it.ld = (uint32_t)n_cols;
+    it.n_rows = n_rows;
+    it.n = (int)n;
+    it.mult = row_mult;
+    it.col_map = keep_cols.data();
+    it.col_exp = exps.data();
+    it.arena_cols = (int)keep_cols.size();
+    // the column sums are formed per distinct column: split to fill the device
+    BBFG_TRY(get_plan(*c, row_mult, n_rows, (int)n, 0, PLAN_SINGLE, &it.plan));
+    double res[2], diag[2];
+    RunResult rr;
+    BBFG_TRY(run_perms(*c, items, 0, false, res, diag, &rr));
+    if (info) {
+        info->rel_err_est = diag[0];
+        info->kappa = diag[1];
+        info->n_addends = it.plan->n_addends;
+        info->n_units = rr.units;
+        info->kernel_ms = rr.kernel_ms;
+    }
+    return write_results(out, res, 1);
+}
+
 double perm_batch_last_kernel_ms(void) { return t_batch_kernel_ms; }
 
 int perm_batch_last_was_graph(void) { return t_batch_graph ? 1 : 0; }

@@ -185,7 +185,9 @@ int batch_waves(Context& c, int bucket, int kind, int* waves)
         *waves = it->second;
         return BBFG_OK;
     }
-    const void* fn = kind == kKindMinors ? walk_minors_fn(bucket) : walk_batch_fn(bucket, kind);
+    const void* fn = kind == kKindMinors ? walk_minors_fn(bucket)
+                     : kind == kKindCols  ? walk_cols_fn(bucket)
+                                          : walk_batch_fn(bucket, kind);
     if (!fn) return set_error(BBFG_ERANGE, "no batch kernel for bucket %d", bucket);
     int blocks = 0;
     BBFG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, kWave, 0));
@@ -291,11 +293,21 @@ int run_perms(Context& c, Workspace& w, std::vector<PermItem>& items, int f32, b
     hipStream_t s = current_stream();
     // leave-one-column-out items (targets > 0) run in their own launches
     const bool minors = items[0].targets > 0;
-    for (auto& it : items)
+    const bool powcols = items[0].col_exp != nullptr;
+    for (auto& it : items) {
         if ((it.targets > 0) != minors || (minors && (single || f32 || it.targets > it.plan->n + 1)))
             return set_error(BBFG_EINVAL, "internal: bad mix of minor items");
-    // columns held per item: the plan's n, plus the left-out column for minors
-    auto cols_of = [&](const PermItem& it) { return it.plan->n + (it.targets > 0 ? 1 : 0); };
+        if ((it.col_exp != nullptr) != powcols || (powcols && (single || f32 || minors || it.arena_cols < 1)))
+            return set_error(BBFG_EINVAL, "internal: bad mix of column-multiplicity items");
+    }
+    // columns held per item: the plan's n, plus the left-out column for minors,
+    // or the distinct columns of an item with column multiplicities
+    auto cols_of = [&](const PermItem& it) {
+        return it.arena_cols > 0 ? it.arena_cols : it.plan->n + (it.targets > 0 ? 1 : 0);
+    };
+    size_t n_colexp = 0;
+    if (powcols)
+        for (auto& it : items) n_colexp += (size_t)it.arena_cols;
     auto stride_of = [](const PermItem& it) { return (uint64_t)(it.targets > 0 ? it.targets : 1); };
 
     // distinct plans (row records are shared between equal shapes; Gray tables
@@ -391,6 +403,7 @@ int run_perms(Context& c, Workspace& w, std::vector<PermItem>& items, int f32, b
     const size_t off_uchunk = single ? 0 : L.add(sizeof(uint32_t) * (nchunk + 1));
     const size_t off_ritem = L.add(sizeof(uint32_t) * (size_t)nres);
     const size_t off_tabs = L.add(std::max<size_t>(1, upload_bytes));
+    const size_t off_cexp = L.add(std::max<size_t>(1, n_colexp));
     BBFG_TRY(w.hmeta.ensure(L.size));
     BBFG_TRY(w.meta.ensure(L.size));
     char* H = w.hmeta.as<char>();
@@ -404,7 +417,8 @@ int run_perms(Context& c, Workspace& w, std::vector<PermItem>& items, int f32, b
         std::memcpy(hr + kv.second.first, kv.first->rows.data(), sizeof(RowInfo) * (size_t)kv.first->r);
     for (const Upload& u : uploads) std::memcpy(H + off_tabs + u.off, u.plan->table->data(), u.bytes);
     uint64_t a_cursor = 0;
-    size_t s_cursor = 0, c_cursor = 0;
+    size_t s_cursor = 0, c_cursor = 0, e_cursor = 0;
+    uint8_t* hx = reinterpret_cast<uint8_t*>(H + off_cexp);
     for (size_t i = 0; i < nitem; ++i) {
         const HostPlan& p = *items[i].plan;
         const auto sl = plan_slot[&p];
@@ -430,6 +444,11 @@ int run_perms(Context& c, Workspace& w, std::vector<PermItem>& items, int f32, b
         d.part_base = part_base[i];
         d.targets = (uint32_t)items[i].targets;
         d.res_base = res_base[i];
+        d.colexp_off = kNoColExp;
+        if (items[i].col_exp) {
+            d.colexp_off = (uint32_t)e_cursor;
+            for (int j = 0; j < nc; ++j) hx[e_cursor++] = items[i].col_exp[j];
+        }
         for (uint64_t t = 0; t < stride_of(items[i]); ++t) hri[res_base[i] + t] = (uint32_t)i;
         PrepItem& q = hp[i];
         std::memset(&q, 0, sizeof q);
@@ -480,6 +499,7 @@ int run_perms(Context& c, Workspace& w, std::vector<PermItem>& items, int f32, b
     std::memset(&W, 0, sizeof W);
     W.descs = reinterpret_cast<const PermDesc*>(D + off_desc);
     W.rowinfo = reinterpret_cast<const RowInfo*>(D + off_row);
+    W.colexp = reinterpret_cast<const uint8_t*>(D + off_cexp);
     W.a = w.arena_d.as<double>();
     W.a2 = w.arena_d.as<double>();
     W.af = w.arena_f.as<float>();
@@ -499,7 +519,7 @@ int run_perms(Context& c, Workspace& w, std::vector<PermItem>& items, int f32, b
         bucket = batch_bucket_max(nmax, f32);
         if (bucket < 0) return set_error(BBFG_ERANGE, "no batch kernel for n=%d", nmax);
         int waves = 1;
-        BBFG_TRY(batch_waves(c, bucket, minors ? kKindMinors : f32, &waves));
+        BBFG_TRY(batch_waves(c, bucket, minors ? kKindMinors : (powcols ? kKindCols : f32), &waves));
         grid = std::min<uint64_t>((uint64_t)waves * (uint64_t)c.n_cu, total_units);
     }
     double* R = w.results.as<double>();
@@ -518,6 +538,7 @@ int run_perms(Context& c, Workspace& w, std::vector<PermItem>& items, int f32, b
         if (timed) BBFG_HIP(hipEventRecord(w.ev0, q));
         if (single) BBFG_HIP(launch_walk_single(items[0].plan->n, f32, (uint32_t)total_units, q, W, 0u));
         else if (minors) BBFG_HIP(launch_walk_minors(bucket, (uint32_t)grid, q, W));
+        else if (powcols) BBFG_HIP(launch_walk_cols(bucket, (uint32_t)grid, q, W));
         else BBFG_HIP(launch_walk_batch(bucket, f32, (uint32_t)grid, q, W));
         if (timed) BBFG_HIP(hipEventRecord(w.ev1, q));
         BBFG_HIP(launch_finalize((uint32_t)nres, q, W.descs, reinterpret_cast<const uint32_t*>(D + off_ritem),
@@ -561,7 +582,8 @@ int run_perms(Context& c, Workspace& w, std::vector<PermItem>& items, int f32, b
             for (size_t i = 0; i < n; ++i) key = (key ^ b[i]) * 1099511628211ull;
         };
         mix(&W, sizeof W);
-        const uint64_t extra[] = {nitem, nres, (uint64_t)single, (uint64_t)minors, (uint64_t)f32, (uint64_t)bucket,
+        const uint64_t extra[] = {nitem, nres, (uint64_t)single, (uint64_t)minors, (uint64_t)powcols, (uint64_t)f32,
+                                  (uint64_t)bucket, off_cexp,
                                   grid, L.size, off_desc, off_row, off_prep, off_src, off_col, off_ubase, off_uorder,
                                   off_uchunk, off_ritem, off_tabs,
                                   (uint64_t)(uintptr_t)H, (uint64_t)(uintptr_t)D, (uint64_t)(uintptr_t)R,

@@ -24,6 +24,7 @@
 #include "internal.hpp"
 #include "kernels.hpp"
 #include "walk_core.hpp"
+#include "walk_batch.hpp"
 #include "walk_device.hpp"
 
 namespace bbfg {
@@ -93,45 +94,6 @@ __global__ __launch_bounds__(kWave) void walk_single_kernel(WalkArgs A, uint32_t
     double r, i, a;
     walk_unit<N, Real>(A, d, u, threadIdx.x & (kWave - 1), r, i, a);
     store_partial(A.partials, d.part_base + u, r, i, a);
-}
-
-// ---------------------------------------------------------------------------
-// batched launch: persistent wavefronts pull global units from a counter
-// (units are numbered longest-first); each unit dispatches on its column count
-// ---------------------------------------------------------------------------
-template <int NMIN, int NMAX, typename Real>
-__device__ __forceinline__ void dispatch_unit(const WalkArgs& A, const PermDesc& d, uint32_t u_local, double& r,
-                                              double& i, double& a)
-{
-    if constexpr (NMIN <= NMAX) {
-        if (d.n == NMIN) {
-            walk_unit<NMIN, Real>(A, d, u_local, threadIdx.x & (kWave - 1), r, i, a);
-        } else {
-            dispatch_unit<NMIN + 1, NMAX, Real>(A, d, u_local, r, i, a);
-        }
-    }
-}
-
-// The loop control is kept free of divergent branches: lane 0 takes the next
-// unit from the counter and hands it to the wavefront through LDS between two
-// barriers, so every lane leaves the loop at the same iteration.
-template <int NMAX, typename Real>
-__global__ __launch_bounds__(kWave) void walk_batch_kernel(WalkArgs A)
-{
-    __shared__ uint32_t next_unit;
-    for (;;) {
-        if (threadIdx.x == 0) next_unit = atomicAdd(A.counter, 1u);
-        __syncthreads();
-        const uint32_t u = __builtin_amdgcn_readfirstlane(next_unit);
-        __syncthreads();
-        if (u >= A.total_units) break;
-        const uint32_t item = item_of_unit(A, u);
-        const PermDesc d = A.descs[item];
-        const uint32_t u_local = u - (uint32_t)d.unit_base;
-        double r = 0.0, i = 0.0, a = 0.0;
-        dispatch_unit<1, NMAX, Real>(A, d, u_local, r, i, a);
-        store_partial_all_lanes(A.partials, d.part_base + u_local, r, i, a);
-    }
 }
 
 __global__ void reset_counter_kernel(uint32_t* counter)
@@ -250,6 +212,25 @@ const void* walk_batch_fn(int bucket, int f32)
     case 48: return reinterpret_cast<const void*>(&walk_batch_kernel<48, double>);
     default: return nullptr;
     }
+}
+
+const void* walk_cols_fn(int bucket)
+{
+    switch (bucket) {
+    case 16: return walk_cols_fn_b16();
+    case 24: return walk_cols_fn_b24();
+    case 32: return walk_cols_fn_b32();
+    case 48: return walk_cols_fn_b48();
+    default: return nullptr;
+    }
+}
+
+hipError_t launch_walk_cols(int bucket, uint32_t grid, hipStream_t s, const WalkArgs& A)
+{
+    const void* fn = walk_cols_fn(bucket);
+    if (!fn) return hipErrorInvalidValue;
+    void* args[] = {const_cast<WalkArgs*>(&A)};
+    return hipLaunchKernel(fn, dim3(grid), dim3(kWave), args, 0, s);
 }
 
 const void* walk_minors_fn(int bucket)

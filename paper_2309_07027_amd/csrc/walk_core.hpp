@@ -120,6 +120,49 @@ BBFG_FN void cprod(const Real* re, const Real* im, Real& pr, Real& pi)
     pi = ci[0];
 }
 
+// prod_j c_j^{N_j} over N distinct column sums with multiplicities N_j >= 1
+// read from ex (uniform): column j enters chain j mod C N_j times, so the
+// product has sum_j N_j - 1 complex multiplies, as for the expanded columns,
+// while the column sums are kept (and updated) once per distinct column.
+template <int N, typename Real>
+BBFG_FN void cprod_pow(const Real* re, const Real* im, kptr<uint8_t> ex, Real& pr, Real& pi)
+{
+    constexpr int C = N >= 12 ? 4 : (N >= 4 ? 2 : 1);
+    Real cr[C], ci[C];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        const int c = j % C;
+        uint32_t e = uniform_u32(ex[j]);
+        if (j < C) {
+            cr[c] = re[j];
+            ci[c] = im[j];
+            e -= 1;
+        }
+        for (; e > 0; --e) {
+            const Real t0 = ci[c] * im[j];
+            const Real t1 = ci[c] * re[j];
+            const Real nr = fmar(cr[c], re[j], -t0);
+            const Real ni = fmar(cr[c], im[j], t1);
+            cr[c] = nr;
+            ci[c] = ni;
+        }
+    }
+#pragma unroll
+    for (int s = 1; s < C; s *= 2) {
+#pragma unroll
+        for (int c = 0; c + s < C; c += 2 * s) {
+            const Real t0 = ci[c] * ci[c + s];
+            const Real t1 = ci[c] * cr[c + s];
+            const Real nr = fmar(cr[c], cr[c + s], -t0);
+            const Real ni = fmar(cr[c], ci[c + s], t1);
+            cr[c] = nr;
+            ci[c] = ni;
+        }
+    }
+    pr = cr[0];
+    pi = ci[0];
+}
+
 // (x / stride) % radix for a 64-bit x; 32-bit arithmetic when x fits.
 BBFG_FN uint32_t digit_of(uint64_t x, uint32_t stride, uint32_t radix)
 {
@@ -190,9 +233,18 @@ BBFG_FN void seed(const WalkArgs& A, const PermDesc& d, uint32_t lane_idx, uint6
     }
 }
 
+// The column multiplicities of d (POW), or a null pointer.
+template <bool POW>
+BBFG_FN kptr<uint8_t> col_exps(const WalkArgs& A, const PermDesc& d)
+{
+    if constexpr (POW) return kconst(A.colexp + d.colexp_off);
+    else return kptr<uint8_t>{};
+}
+
 // One work unit of permanent d, for one lane: the lane's sum of weighted
-// addends and the sum of their magnitudes (|re| + |im|).
-template <int N, typename Real>
+// addends and the sum of their magnitudes (|re| + |im|).  POW: the N columns
+// carry multiplicities (d.colexp_off), the product is prod_j c_j^{N_j}.
+template <int N, typename Real, bool POW = false>
 BBFG_FN void walk_unit(const WalkArgs& A, const PermDesc& d, uint32_t u_local, uint32_t lane, double& out_r,
                        double& out_i, double& out_a)
 {
@@ -209,6 +261,7 @@ BBFG_FN void walk_unit(const WalkArgs& A, const PermDesc& d, uint32_t u_local, u
 
     kptr<TabEntry> tab = kconst(d.tab);
     kptr<Real> a2 = kconst(RowsOf<Real>::a2(A) + 2 * d.a2_off);
+    const kptr<uint8_t> ex = col_exps<POW>(A, d);
     const uint32_t Q = d.Q;
 
     double accr = 0.0, acci = 0.0, acca = 0.0;
@@ -224,7 +277,8 @@ BBFG_FN void walk_unit(const WalkArgs& A, const PermDesc& d, uint32_t u_local, u
         double sr, si, sa;
         {
             Real pr, pi;
-            cprod<N, Real>(re, im, pr, pi);
+            if constexpr (POW) cprod_pow<N, Real>(re, im, ex, pr, pi);
+            else cprod<N, Real>(re, im, pr, pi);
             const double s = tab[t0].s;
             sr = s * (double)pr;
             si = s * (double)pi;
@@ -240,7 +294,8 @@ BBFG_FN void walk_unit(const WalkArgs& A, const PermDesc& d, uint32_t u_local, u
                 im[j] += row[2 * j + 1];
             }
             Real pr, pi;
-            cprod<N, Real>(re, im, pr, pi);
+            if constexpr (POW) cprod_pow<N, Real>(re, im, ex, pr, pi);
+            else cprod<N, Real>(re, im, pr, pi);
             sr = __builtin_fma(s, (double)pr, sr);
             si = __builtin_fma(s, (double)pi, si);
             sa = __builtin_fma(__builtin_fabs(s), __builtin_fabs((double)pr) + __builtin_fabs((double)pi), sa);

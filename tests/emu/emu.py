@@ -54,3 +54,20 @@ def run_minors(A, M, l_batch: int, slots: int = 1):
         raise RuntimeError(f"walk_emu failed ({p.returncode}): {p.stderr[-2000:]}")
     vals = p.stdout.split()
     return np.array([complex(float.fromhex(vals[2 * i]), float.fromhex(vals[2 * i + 1])) for i in range(n)])
+
+
+def run_cols(A, M, N, slots: int, l_batch: int = 0):
+    """Emulated walk with column multiplicities N (A holds the distinct columns):
+    (value, rel_err_est, kappa, units)."""
+    A = np.ascontiguousarray(np.asarray(A, dtype=np.complex128))
+    r, n = A.shape
+    lines = [f"{r} {n} {int(slots)} 0 {int(l_batch)} 2", " ".join(str(int(m)) for m in M),
+             " ".join(str(int(x)) for x in N)]
+    lines.append(" ".join(f"{float(x.real).hex()} {float(x.imag).hex()}" for x in A.ravel()))
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0")
+    p = subprocess.run([str(EXE)], input="\n".join(lines) + "\n", capture_output=True, text=True, env=env,
+                       timeout=600)
+    if p.returncode != 0:
+        raise RuntimeError(f"walk_emu failed ({p.returncode}): {p.stderr[-2000:]}")
+    re_, im_, err, kappa, units = p.stdout.split()
+    return complex(float.fromhex(re_), float.fromhex(im_)), float.fromhex(err), float.fromhex(kappa), int(units)

@@ -13,6 +13,8 @@
 //         item as a batched launch does (fixed unit length), 0 as a single launch.
 //         minors = 1: the multiplicities sum to n - 1 and the n leave-one-column-
 //         out permanents are formed as the batched minors walk does (FP64).
+//         minors = 2: column multiplicities; one more line of n column
+//         multiplicities (>= 1) follows the row multiplicities (FP64).
 // stdout: re im rel_err_est kappa units   (hex floats, then an integer), or for
 //         minors n lines "re im" (permanent without column l, l = 0 .. n-1)
 #include <algorithm>
@@ -39,28 +41,54 @@ void run_unit(const WalkArgs& W, const PermDesc& d, uint32_t u, uint32_t lane, d
 }
 
 int read_case(int& n_rows, int& n, long long& slots, int& f32, long long& l_batch, int& minors,
-              std::vector<int32_t>& M, std::vector<double>& A)
+              std::vector<int32_t>& M, std::vector<int32_t>& N, std::vector<double>& A)
 {
     if (std::scanf("%d %d %lld %d %lld %d", &n_rows, &n, &slots, &f32, &l_batch, &minors) != 6) return 1;
     M.resize((size_t)n_rows);
     for (int i = 0; i < n_rows; ++i)
         if (std::scanf("%d", &M[(size_t)i]) != 1) return 1;
+    if (minors == 2) {
+        N.resize((size_t)n);
+        for (int j = 0; j < n; ++j)
+            if (std::scanf("%d", &N[(size_t)j]) != 1) return 1;
+    }
     A.resize(2 * (size_t)n_rows * (size_t)n);
     for (size_t i = 0; i < A.size(); ++i)
         if (std::scanf("%la", &A[i]) != 1) return 1;
     return 0;
 }
 
+template <int NMIN, int NMAX>
+void run_unit_pow(const WalkArgs& W, const PermDesc& d, uint32_t u, uint32_t lane, double& r, double& i, double& a)
+{
+    if constexpr (NMIN <= NMAX) {
+        if (d.n == NMIN) walk_unit<NMIN, double, true>(W, d, u, lane, r, i, a);
+        else run_unit_pow<NMIN + 1, NMAX>(W, d, u, lane, r, i, a);
+    }
+}
+
+// N (optional): multiplicities of the n distinct columns; the plan is then that
+// of sum(N) columns and the walk forms prod_j c_j^{N_j} (FP64 only).
 template <typename Real>
 int emulate(int n_rows, int n, long long slots, long long l_batch, const std::vector<int32_t>& M,
-            const std::vector<double>& A)
+            const std::vector<double>& A, const std::vector<int32_t>& N = {})
 {
+    const bool pow = !N.empty();
+    int n_total = n;
+    std::vector<uint8_t> colexp;
+    if (pow) {
+        n_total = 0;
+        for (int32_t e : N) {
+            n_total += e;
+            colexp.push_back((uint8_t)e);
+        }
+    }
     const int f32 = sizeof(Real) == 4 ? 1 : 0;
     HostPlan P;
     std::string err;
     PlanParams pp;
     pp.l_batch = (uint64_t)l_batch;
-    int rc = build_plan(M.data(), n_rows, n, (uint64_t)slots, pp, P, err);
+    int rc = build_plan(M.data(), n_rows, n_total, (uint64_t)slots, pp, P, err);
     if (rc) {
         std::fprintf(stderr, "plan error %d: %s\n", rc, err.c_str());
         return 2;
@@ -111,8 +139,9 @@ int emulate(int n_rows, int n, long long slots, long long l_batch, const std::ve
     d.Q = P.Q;
     d.lane_product = P.lane_product;
     d.groups = P.groups;
-    d.scale = std::ldexp(1.0, 1 - n);
+    d.scale = std::ldexp(1.0, 1 - n_total);
     d.err_coeff = P.err_coeff * (f32 ? 0x1.0p-24 : 0x1.0p-53);
+    d.colexp_off = pow ? 0u : kNoColExp;
 
     WalkArgs W;
     std::memset(&W, 0, sizeof W);
@@ -130,6 +159,10 @@ int emulate(int n_rows, int n, long long slots, long long l_batch, const std::ve
     emu_register(P.table->data(), sizeof(TabEntry) * P.table->size());
     emu_register(binom.data(), sizeof(double) * binom.size());
     emu_register(arena.data(), sizeof(Real) * arena.size());
+    if (pow) {
+        W.colexp = colexp.data();
+        emu_register(colexp.data(), colexp.size());
+    }
 
     std::vector<double> part((size_t)P.units * kPartialDoubles);
     for (uint64_t u = 0; u < P.units; ++u) {
@@ -137,7 +170,12 @@ int emulate(int n_rows, int n, long long slots, long long l_batch, const std::ve
         double sa[kWave];
         for (uint32_t lane = 0; lane < (uint32_t)kWave; ++lane) {
             double x = 0, y = 0, z = 0;
-            run_unit<1, kMaxN, Real>(W, d, (uint32_t)u, lane, x, y, z);
+            if constexpr (sizeof(Real) == 8) {
+                if (pow) run_unit_pow<1, kMaxN>(W, d, (uint32_t)u, lane, x, y, z);
+                else run_unit<1, kMaxN, Real>(W, d, (uint32_t)u, lane, x, y, z);
+            } else {
+                run_unit<1, kMaxN, Real>(W, d, (uint32_t)u, lane, x, y, z);
+            }
             sr[lane] = {x, 0.0};
             si[lane] = {y, 0.0};
             sa[lane] = z;
@@ -359,12 +397,13 @@ int main()
 {
     int n_rows = 0, n = 0, f32 = 0, minors = 0;
     long long slots = 0, l_batch = 0;
-    std::vector<int32_t> M;
+    std::vector<int32_t> M, N;
     std::vector<double> A;
-    if (read_case(n_rows, n, slots, f32, l_batch, minors, M, A)) {
+    if (read_case(n_rows, n, slots, f32, l_batch, minors, M, N, A)) {
         std::fprintf(stderr, "bad input\n");
         return 2;
     }
-    if (minors) return emulate_minors(n_rows, n, slots, l_batch, M, A);
+    if (minors == 1) return emulate_minors(n_rows, n, slots, l_batch, M, A);
+    if (minors == 2) return emulate<double>(n_rows, n, slots, l_batch, M, A, N);
     return f32 ? emulate<float>(n_rows, n, slots, l_batch, M, A) : emulate<double>(n_rows, n, slots, l_batch, M, A);
 }

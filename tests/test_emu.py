@@ -107,3 +107,19 @@ def test_minors_walk_matches_oracle(oracle, modes, Ks):
             for l, (ref, absum) in enumerate(refs):
                 bar = max(TOL, absum / abs(ref) * (K + 64) * 2.0 ** -53)
                 assert rel(got[l], ref) <= bar, (K, l, M, L)
+
+
+@pytest.mark.parametrize("seed", [31, 32])
+def test_column_multiplicities_match_oracle(oracle, seed):
+    """The walk with column multiplicities (prod_j c_j^{N_j} over distinct columns,
+    Eq. bbfgrepeated) against the oracle's permanent of the column-expanded matrix."""
+    rng = np.random.default_rng(seed)
+    for n in (1, 2, 5, 9, 14, 17):
+        rows, M = I.bunch(rng.integers(0, 60, n), 60)
+        cols, N = I.bunch(rng.integers(0, 9, n), 9)
+        u = I.haar_from_rng(rng, 60)
+        A = np.ascontiguousarray(u[rows][:, cols])
+        ref = oracle.perm_generalized(np.repeat(A, N, axis=1), M)
+        for slots, L in ((1, 64), (2048, 0)):
+            v, err, kappa, units = emu.run_cols(A, M, N, slots, L)
+            assert rel(v, ref) <= TOL, (n, M.tolist(), N.tolist(), slots, L)

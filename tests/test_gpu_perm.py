@@ -379,3 +379,41 @@ def test_results_independent_of_cache_flushes():
             assert np.array_equal(B.bs_sample(U, occ, 8, 0.0, 99), s_ref)
     finally:
         B.set_cache_limits(0, 0)
+
+
+def test_column_multiplicities_vs_oracle_and_expansion(oracle):
+    """perm_bbfg_cols (Eq. bbfgrepeated with row and column multiplicities)
+    against the oracle on the column-expanded matrix, against perm_bbfg on the
+    expanded matrix, and bitwise against the CPU emulation of its kernel."""
+    from tests.emu import emu
+    emu.build()
+    rng = np.random.default_rng(606)
+    for n, modes_in in ((6, 4), (12, 6), (18, 10), (24, 30), (28, 14)):
+        rows, M = I.bunch(rng.integers(0, 60, n), 60)
+        cols, N = I.bunch(rng.integers(0, modes_in, n), modes_in)
+        u = I.haar_from_rng(rng, 60)
+        A = np.ascontiguousarray(u[rows][:, cols])
+        say(f"case cols n={n} M={M.tolist()} N={N.tolist()}")
+        v, info = B.perm_bbfg_cols(A, M, N, with_info=True)
+        Ax = np.ascontiguousarray(np.repeat(A, N, axis=1))
+        vx, infox = B.perm_bbfg(Ax, M, with_info=True)
+        assert rel(v, vx) <= max(TOL, 2 * infox["rel_err_est"]), n
+        if n <= 18:
+            ref = oracle.perm_generalized(Ax, M)
+            assert rel(v, ref) <= TOL, n
+        waves, ncu = B.walk_occupancy(int(N.sum()))  # the split is planned for n = sum(N) columns
+        e, *_ = emu.run_cols(A, M, N, waves * ncu)
+        assert v == e, (n, v, e)
+
+
+def test_column_multiplicities_edges():
+    A = np.ones((2, 3), dtype=np.complex128)
+    assert B.perm_bbfg_cols(A, [2, 1], [1, 1, 1]) == pytest.approx(6)      # perm(J_3)
+    assert B.perm_bbfg_cols(A, [2, 1], [3, 0, 0]) == pytest.approx(6)      # zero columns dropped
+    assert B.perm_bbfg_cols(A, [0, 0], [0, 0, 0]) == 1                      # empty permanent
+    with pytest.raises(B.BBFGError):
+        B.perm_bbfg_cols(A, [2, 1], [1, 1, 0])                              # sums differ
+    with pytest.raises(B.BBFGError):
+        B.perm_bbfg_cols(A, [2, 1], [2, 2, -1])
+    with pytest.raises(B.BBFGError):
+        B.perm_bbfg_cols(np.ones((1, 1), dtype=np.complex128), [49], [49])  # beyond BBFG_MAX_N
