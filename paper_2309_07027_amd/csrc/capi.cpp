@@ -254,16 +254,12 @@ int perm_bbfg_cols(const bbfg_c128* A, int32_t n_rows, const int32_t* row_mult, 
     if (n_cols < 0) return set_error(BBFG_EINVAL, "n_cols = %d < 0", n_cols);
     if (n_cols > 0 && !col_mult) return set_error(BBFG_EINVAL, "col_mult is NULL");
     int64_t n = 0;
-    std::vector<int32_t> keep_cols;
-    std::vector<uint8_t> exps;
+    std::vector<int32_t> kept;  // distinct columns with N_j > 0
     for (int32_t j = 0; j < n_cols; ++j) {
         if (col_mult[j] < 0) return set_error(BBFG_EINVAL, "col_mult[%d] = %d < 0", j, col_mult[j]);
         n += col_mult[j];
         if (n > kMaxN) return set_error(BBFG_ERANGE, "sum(col_mult) exceeds the maximum %d", kMaxN);
-        if (col_mult[j] > 0) {
-            keep_cols.push_back(j);
-            exps.push_back((uint8_t)col_mult[j]);
-        }
+        if (col_mult[j] > 0) kept.push_back(j);
     }
     BBFG_TRY(validate_shape(row_mult, n_rows, (int32_t)n, kMaxN));
     if (info) std::memset(info, 0, sizeof *info);
@@ -281,6 +277,10 @@ int perm_bbfg_cols(const bbfg_c128* A, int32_t n_rows, const int32_t* row_mult, 
     std::lock_guard<std::recursive_mutex> lk(c->mu);
     const double* Ad = nullptr;
     BBFG_TRY(device_view(*c, A, (uint64_t)n_rows * (uint64_t)n_cols, &Ad));
+    bool uniform = true;
+    for (int32_t j : kept) uniform = uniform && col_mult[j] == col_mult[kept[0]];
+    const int e = col_mult[kept[0]];
+    std::vector<int32_t> cmap;
     std::vector<PermItem> items(1);
     PermItem& it = items[0];
     it.src = Ad;
@@ -288,14 +288,26 @@ int perm_bbfg_cols(const bbfg_c128* A, int32_t n_rows, const int32_t* row_mult, 
     it.n_rows = n_rows;
     it.n = (int)n;
     it.mult = row_mult;
-    it.col_map = keep_cols.data();
-    it.col_exp = exps.data();
-    it.arena_cols = (int)keep_cols.size();
-    // the column sums are formed per distinct column: split to fill the device
+    bool single = true;
+    if (uniform && e >= 2) {
+        // (prod_j c_j)^e over the distinct columns: one sum per distinct column
+        // and about n / e complex products per addend
+        cmap = kept;
+        it.col_pow = e;
+        it.arena_cols = (int)kept.size();
+        single = false;
+    } else {
+        // mixed multiplicities: the column-expanded matrix (repeated columns
+        // gathered on the device) -- per-column powers inside the product would
+        // serialise its multiply chains
+        for (int32_t j : kept)
+            for (int32_t t = 0; t < col_mult[j]; ++t) cmap.push_back(j);
+    }
+    it.col_map = cmap.data();
     BBFG_TRY(get_plan(*c, row_mult, n_rows, (int)n, 0, PLAN_SINGLE, &it.plan));
     double res[2], diag[2];
     RunResult rr;
-    BBFG_TRY(run_perms(*c, items, 0, false, res, diag, &rr));
+    BBFG_TRY(run_perms(*c, items, 0, single, res, diag, &rr));
     if (info) {
         info->rel_err_est = diag[0];
         info->kappa = diag[1];

@@ -63,11 +63,10 @@ struct PermDesc {
     uint32_t targets;        // 0: one permanent of the n columns.  G > 0: the G permanents that each
                              //   leave out one of the last G columns (Laplace minors)
     uint32_t res_base;       // index of the first result
-    uint32_t colexp_off;     // column multiplicities: N_j of the n (distinct) columns at
-                             //   colexp[colexp_off + j] (Eq. bbfgrepeated); kNoColExp: all 1
+    uint32_t col_pow;        // every one of the n (distinct) columns has multiplicity col_pow
+                             //   (Eq. bbfgrepeated): the product is (prod_j c_j)^col_pow
     uint32_t pad;
 };
-constexpr uint32_t kNoColExp = 0xFFFFFFFFu;
 
 // Leave-one-column-out walks over K columns cover the targets in groups of
 // minor_group(K): one group keeps K column sums, G prefix products and G
@@ -114,7 +113,6 @@ struct PrepItem {
 struct WalkArgs {
     const PermDesc* descs;
     const RowInfo* rowinfo;
-    const uint8_t* colexp;  // column multiplicities (items with colexp_off != kNoColExp)
     const double* a;     // FP64 kept rows (interleaved complex)
     const double* a2;    // FP64 +-2a rows
     const float* af;     // FP32 copies

@@ -15,7 +15,7 @@ int batch_bucket_max(int nmax, int f32);
 
 hipError_t launch_walk_single(int n, int f32, uint32_t grid, hipStream_t s, const WalkArgs& A, uint32_t item);
 hipError_t launch_walk_batch(int bucket, int f32, uint32_t grid, hipStream_t s, const WalkArgs& A);
-// column multiplicities (items with colexp_off != kNoColExp), FP64, same buckets
+// uniform column multiplicities (items with col_pow >= 2), FP64, same buckets
 const void* walk_cols_fn(int bucket);
 const void* walk_cols_fn_b16();
 const void* walk_cols_fn_b24();

@@ -293,11 +293,12 @@ int run_perms(Context& c, Workspace& w, std::vector<PermItem>& items, int f32, b
     hipStream_t s = current_stream();
     // leave-one-column-out items (targets > 0) run in their own launches
     const bool minors = items[0].targets > 0;
-    const bool powcols = items[0].col_exp != nullptr;
+    const bool powcols = items[0].col_pow >= 2;
     for (auto& it : items) {
         if ((it.targets > 0) != minors || (minors && (single || f32 || it.targets > it.plan->n + 1)))
             return set_error(BBFG_EINVAL, "internal: bad mix of minor items");
-        if ((it.col_exp != nullptr) != powcols || (powcols && (single || f32 || minors || it.arena_cols < 1)))
+        if ((it.col_pow >= 2) != powcols ||
+            (powcols && (single || f32 || minors || it.arena_cols < 1 || it.arena_cols * it.col_pow != it.plan->n)))
             return set_error(BBFG_EINVAL, "internal: bad mix of column-multiplicity items");
     }
     // columns held per item: the plan's n, plus the left-out column for minors,
@@ -305,9 +306,6 @@ int run_perms(Context& c, Workspace& w, std::vector<PermItem>& items, int f32, b
     auto cols_of = [&](const PermItem& it) {
         return it.arena_cols > 0 ? it.arena_cols : it.plan->n + (it.targets > 0 ? 1 : 0);
     };
-    size_t n_colexp = 0;
-    if (powcols)
-        for (auto& it : items) n_colexp += (size_t)it.arena_cols;
     auto stride_of = [](const PermItem& it) { return (uint64_t)(it.targets > 0 ? it.targets : 1); };
 
     // distinct plans (row records are shared between equal shapes; Gray tables
@@ -403,7 +401,6 @@ int run_perms(Context& c, Workspace& w, std::vector<PermItem>& items, int f32, b
     const size_t off_uchunk = single ? 0 : L.add(sizeof(uint32_t) * (nchunk + 1));
     const size_t off_ritem = L.add(sizeof(uint32_t) * (size_t)nres);
     const size_t off_tabs = L.add(std::max<size_t>(1, upload_bytes));
-    const size_t off_cexp = L.add(std::max<size_t>(1, n_colexp));
     BBFG_TRY(w.hmeta.ensure(L.size));
     BBFG_TRY(w.meta.ensure(L.size));
     char* H = w.hmeta.as<char>();
@@ -417,8 +414,7 @@ int run_perms(Context& c, Workspace& w, std::vector<PermItem>& items, int f32, b
         std::memcpy(hr + kv.second.first, kv.first->rows.data(), sizeof(RowInfo) * (size_t)kv.first->r);
     for (const Upload& u : uploads) std::memcpy(H + off_tabs + u.off, u.plan->table->data(), u.bytes);
     uint64_t a_cursor = 0;
-    size_t s_cursor = 0, c_cursor = 0, e_cursor = 0;
-    uint8_t* hx = reinterpret_cast<uint8_t*>(H + off_cexp);
+    size_t s_cursor = 0, c_cursor = 0;
     for (size_t i = 0; i < nitem; ++i) {
         const HostPlan& p = *items[i].plan;
         const auto sl = plan_slot[&p];
@@ -444,11 +440,7 @@ int run_perms(Context& c, Workspace& w, std::vector<PermItem>& items, int f32, b
         d.part_base = part_base[i];
         d.targets = (uint32_t)items[i].targets;
         d.res_base = res_base[i];
-        d.colexp_off = kNoColExp;
-        if (items[i].col_exp) {
-            d.colexp_off = (uint32_t)e_cursor;
-            for (int j = 0; j < nc; ++j) hx[e_cursor++] = items[i].col_exp[j];
-        }
+        d.col_pow = items[i].col_pow >= 2 ? (uint32_t)items[i].col_pow : 1u;
         for (uint64_t t = 0; t < stride_of(items[i]); ++t) hri[res_base[i] + t] = (uint32_t)i;
         PrepItem& q = hp[i];
         std::memset(&q, 0, sizeof q);
@@ -499,7 +491,6 @@ int run_perms(Context& c, Workspace& w, std::vector<PermItem>& items, int f32, b
     std::memset(&W, 0, sizeof W);
     W.descs = reinterpret_cast<const PermDesc*>(D + off_desc);
     W.rowinfo = reinterpret_cast<const RowInfo*>(D + off_row);
-    W.colexp = reinterpret_cast<const uint8_t*>(D + off_cexp);
     W.a = w.arena_d.as<double>();
     W.a2 = w.arena_d.as<double>();
     W.af = w.arena_f.as<float>();
@@ -583,7 +574,7 @@ int run_perms(Context& c, Workspace& w, std::vector<PermItem>& items, int f32, b
         };
         mix(&W, sizeof W);
         const uint64_t extra[] = {nitem, nres, (uint64_t)single, (uint64_t)minors, (uint64_t)powcols, (uint64_t)f32,
-                                  (uint64_t)bucket, off_cexp,
+                                  (uint64_t)bucket,
                                   grid, L.size, off_desc, off_row, off_prep, off_src, off_col, off_ubase, off_uorder,
                                   off_uchunk, off_ritem, off_tabs,
                                   (uint64_t)(uintptr_t)H, (uint64_t)(uintptr_t)D, (uint64_t)(uintptr_t)R,

@@ -153,7 +153,7 @@ int walk_slots(Context& c, int n, int f32, uint64_t* slots);
 // Resident wavefronts per CU of a batch kernel: kind = 0 (FP64), 1 (FP32) or
 // kKindMinors (leave-one-column-out walks).
 constexpr int kKindMinors = 2;
-constexpr int kKindCols = 3;  // column multiplicities
+constexpr int kKindCols = 3;  // uniform column multiplicities
 int batch_waves(Context& c, int bucket, int kind, int* waves);
 // kind = 0 (FP64), 1 (FP32) or BBFG_MINORS: selects the tuned unit length of
 // PLAN_BATCH plans (plans of different kinds are cached separately).
@@ -189,10 +189,10 @@ struct PermItem {
     // lists n + 1) and the item yields the G permanents that each leave out one
     // of its last G columns; the plan is that of the n-column permanents.
     int targets = 0;
-    // Column multiplicities: the matrix has arena_cols distinct columns (col_map
-    // lists them when given) with multiplicities col_exp[j] >= 1 summing to the
-    // plan's n (Eq. bbfgrepeated); null: every column once.
-    const uint8_t* col_exp = nullptr;
+    // Column multiplicities: col_pow >= 2 means the matrix has arena_cols
+    // distinct columns (col_map lists them when given), each with multiplicity
+    // col_pow, arena_cols * col_pow = the plan's n (Eq. bbfgrepeated).
+    int col_pow = 0;
     int arena_cols = 0;
     std::shared_ptr<const HostPlan> plan;
 };

@@ -120,47 +120,30 @@ BBFG_FN void cprod(const Real* re, const Real* im, Real& pr, Real& pi)
     pi = ci[0];
 }
 
-// prod_j c_j^{N_j} over N distinct column sums with multiplicities N_j >= 1
-// read from ex (uniform): column j enters chain j mod C N_j times, so the
-// product has sum_j N_j - 1 complex multiplies, as for the expanded columns,
-// while the column sums are kept (and updated) once per distinct column.
-template <int N, typename Real>
-BBFG_FN void cprod_pow(const Real* re, const Real* im, kptr<uint8_t> ex, Real& pr, Real& pi)
+// z^e for a uniform integer e >= 1 by binary powering (most significant bit
+// first): floor(log2 e) squarings and popcount(e) - 1 multiplies.
+template <typename Real>
+BBFG_FN void cpow_uint(Real& zr, Real& zi, uint32_t e)
 {
-    constexpr int C = N >= 12 ? 4 : (N >= 4 ? 2 : 1);
-    Real cr[C], ci[C];
-#pragma unroll
-    for (int j = 0; j < N; ++j) {
-        const int c = j % C;
-        uint32_t e = uniform_u32(ex[j]);
-        if (j < C) {
-            cr[c] = re[j];
-            ci[c] = im[j];
-            e -= 1;
-        }
-        for (; e > 0; --e) {
-            const Real t0 = ci[c] * im[j];
-            const Real t1 = ci[c] * re[j];
-            const Real nr = fmar(cr[c], re[j], -t0);
-            const Real ni = fmar(cr[c], im[j], t1);
-            cr[c] = nr;
-            ci[c] = ni;
-        }
-    }
-#pragma unroll
-    for (int s = 1; s < C; s *= 2) {
-#pragma unroll
-        for (int c = 0; c + s < C; c += 2 * s) {
-            const Real t0 = ci[c] * ci[c + s];
-            const Real t1 = ci[c] * cr[c + s];
-            const Real nr = fmar(cr[c], cr[c + s], -t0);
-            const Real ni = fmar(cr[c], ci[c + s], t1);
-            cr[c] = nr;
-            ci[c] = ni;
+    const Real br = zr, bi = zi;
+    int top = 31;
+    while (top > 0 && !((e >> top) & 1u)) --top;
+    for (int b = top - 1; b >= 0; --b) {
+        const Real t0 = zi * zi;
+        const Real t1 = zr * zi;
+        const Real sr = fmar(zr, zr, -t0);
+        const Real si = t1 + t1;
+        zr = sr;
+        zi = si;
+        if ((e >> b) & 1u) {
+            const Real u0 = zi * bi;
+            const Real u1 = zi * br;
+            const Real nr = fmar(zr, br, -u0);
+            const Real ni = fmar(zr, bi, u1);
+            zr = nr;
+            zi = ni;
         }
     }
-    pr = cr[0];
-    pi = ci[0];
 }
 
 // (x / stride) % radix for a 64-bit x; 32-bit arithmetic when x fits.
@@ -233,17 +216,9 @@ BBFG_FN void seed(const WalkArgs& A, const PermDesc& d, uint32_t lane_idx, uint6
     }
 }
 
-// The column multiplicities of d (POW), or a null pointer.
-template <bool POW>
-BBFG_FN kptr<uint8_t> col_exps(const WalkArgs& A, const PermDesc& d)
-{
-    if constexpr (POW) return kconst(A.colexp + d.colexp_off);
-    else return kptr<uint8_t>{};
-}
-
 // One work unit of permanent d, for one lane: the lane's sum of weighted
-// addends and the sum of their magnitudes (|re| + |im|).  POW: the N columns
-// carry multiplicities (d.colexp_off), the product is prod_j c_j^{N_j}.
+// addends and the sum of their magnitudes (|re| + |im|).  POW: each of the N
+// columns has multiplicity d.col_pow, the product is (prod_j c_j)^col_pow.
 template <int N, typename Real, bool POW = false>
 BBFG_FN void walk_unit(const WalkArgs& A, const PermDesc& d, uint32_t u_local, uint32_t lane, double& out_r,
                        double& out_i, double& out_a)
@@ -261,7 +236,7 @@ BBFG_FN void walk_unit(const WalkArgs& A, const PermDesc& d, uint32_t u_local, u
 
     kptr<TabEntry> tab = kconst(d.tab);
     kptr<Real> a2 = kconst(RowsOf<Real>::a2(A) + 2 * d.a2_off);
-    const kptr<uint8_t> ex = col_exps<POW>(A, d);
+    const uint32_t cpow = POW ? uniform_u32(d.col_pow) : 1u;
     const uint32_t Q = d.Q;
 
     double accr = 0.0, acci = 0.0, acca = 0.0;
@@ -277,8 +252,8 @@ BBFG_FN void walk_unit(const WalkArgs& A, const PermDesc& d, uint32_t u_local, u
         double sr, si, sa;
         {
             Real pr, pi;
-            if constexpr (POW) cprod_pow<N, Real>(re, im, ex, pr, pi);
-            else cprod<N, Real>(re, im, pr, pi);
+            cprod<N, Real>(re, im, pr, pi);
+            if constexpr (POW) cpow_uint<Real>(pr, pi, cpow);
             const double s = tab[t0].s;
             sr = s * (double)pr;
             si = s * (double)pi;
@@ -294,8 +269,8 @@ BBFG_FN void walk_unit(const WalkArgs& A, const PermDesc& d, uint32_t u_local, u
                 im[j] += row[2 * j + 1];
             }
             Real pr, pi;
-            if constexpr (POW) cprod_pow<N, Real>(re, im, ex, pr, pi);
-            else cprod<N, Real>(re, im, pr, pi);
+            cprod<N, Real>(re, im, pr, pi);
+            if constexpr (POW) cpow_uint<Real>(pr, pi, cpow);
             sr = __builtin_fma(s, (double)pr, sr);
             si = __builtin_fma(s, (double)pi, si);
             sa = __builtin_fma(__builtin_fabs(s), __builtin_fabs((double)pr) + __builtin_fabs((double)pi), sa);

@@ -14,7 +14,9 @@
 //         minors = 1: the multiplicities sum to n - 1 and the n leave-one-column-
 //         out permanents are formed as the batched minors walk does (FP64).
 //         minors = 2: column multiplicities; one more line of n column
-//         multiplicities (>= 1) follows the row multiplicities (FP64).
+//         multiplicities (>= 1) follows the row multiplicities (FP64).  As the
+//         library does, equal multiplicities e >= 2 use (prod_j c_j)^e over the
+//         distinct columns, other ones the column-expanded matrix.
 // stdout: re im rel_err_est kappa units   (hex floats, then an integer), or for
 //         minors n lines "re im" (permanent without column l, l = 0 .. n-1)
 #include <algorithm>
@@ -67,22 +69,15 @@ void run_unit_pow(const WalkArgs& W, const PermDesc& d, uint32_t u, uint32_t lan
     }
 }
 
-// N (optional): multiplicities of the n distinct columns; the plan is then that
-// of sum(N) columns and the walk forms prod_j c_j^{N_j} (FP64 only).
+// N (optional): the same multiplicity e = N[0] >= 2 for each of the n distinct
+// columns; the plan is then that of n * e columns and the walk forms
+// (prod_j c_j)^e (FP64 only).
 template <typename Real>
 int emulate(int n_rows, int n, long long slots, long long l_batch, const std::vector<int32_t>& M,
             const std::vector<double>& A, const std::vector<int32_t>& N = {})
 {
     const bool pow = !N.empty();
-    int n_total = n;
-    std::vector<uint8_t> colexp;
-    if (pow) {
-        n_total = 0;
-        for (int32_t e : N) {
-            n_total += e;
-            colexp.push_back((uint8_t)e);
-        }
-    }
+    const int n_total = pow ? n * N[0] : n;
     const int f32 = sizeof(Real) == 4 ? 1 : 0;
     HostPlan P;
     std::string err;
@@ -141,7 +136,7 @@ int emulate(int n_rows, int n, long long slots, long long l_batch, const std::ve
     d.groups = P.groups;
     d.scale = std::ldexp(1.0, 1 - n_total);
     d.err_coeff = P.err_coeff * (f32 ? 0x1.0p-24 : 0x1.0p-53);
-    d.colexp_off = pow ? 0u : kNoColExp;
+    d.col_pow = pow ? (uint32_t)N[0] : 1u;
 
     WalkArgs W;
     std::memset(&W, 0, sizeof W);
@@ -159,10 +154,6 @@ int emulate(int n_rows, int n, long long slots, long long l_batch, const std::ve
     emu_register(P.table->data(), sizeof(TabEntry) * P.table->size());
     emu_register(binom.data(), sizeof(double) * binom.size());
     emu_register(arena.data(), sizeof(Real) * arena.size());
-    if (pow) {
-        W.colexp = colexp.data();
-        emu_register(colexp.data(), colexp.size());
-    }
 
     std::vector<double> part((size_t)P.units * kPartialDoubles);
     for (uint64_t u = 0; u < P.units; ++u) {
@@ -404,6 +395,21 @@ int main()
         return 2;
     }
     if (minors == 1) return emulate_minors(n_rows, n, slots, l_batch, M, A);
-    if (minors == 2) return emulate<double>(n_rows, n, slots, l_batch, M, A, N);
+    if (minors == 2) {
+        bool uniform = true;
+        for (int32_t e : N) uniform = uniform && e == N[0];
+        if (uniform && N[0] >= 2) return emulate<double>(n_rows, n, slots, l_batch, M, A, N);
+        // mixed multiplicities: the column-expanded matrix
+        std::vector<double> X;
+        int nx = 0;
+        for (int32_t e : N) nx += e;
+        for (int i = 0; i < n_rows; ++i)
+            for (int j = 0; j < n; ++j)
+                for (int t = 0; t < N[(size_t)j]; ++t) {
+                    X.push_back(A[2 * ((size_t)i * n + j)]);
+                    X.push_back(A[2 * ((size_t)i * n + j) + 1]);
+                }
+        return emulate<double>(n_rows, nx, slots, l_batch, M, X);
+    }
     return f32 ? emulate<float>(n_rows, n, slots, l_batch, M, A) : emulate<double>(n_rows, n, slots, l_batch, M, A);
 }

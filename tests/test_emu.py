@@ -111,12 +111,17 @@ def test_minors_walk_matches_oracle(oracle, modes, Ks):
 
 @pytest.mark.parametrize("seed", [31, 32])
 def test_column_multiplicities_match_oracle(oracle, seed):
-    """The walk with column multiplicities (prod_j c_j^{N_j} over distinct columns,
-    Eq. bbfgrepeated) against the oracle's permanent of the column-expanded matrix."""
+    """Column multiplicities (Eq. bbfgrepeated) against the oracle's permanent of
+    the column-expanded matrix: equal multiplicities e use (prod_j c_j)^e over the
+    distinct columns, mixed ones the expanded matrix."""
     rng = np.random.default_rng(seed)
-    for n in (1, 2, 5, 9, 14, 17):
+    cases = [(n, None) for n in (1, 2, 5, 9, 14, 17)] + [(n, e) for n, e in ((4, 2), (12, 2), (15, 3), (16, 4), (18, 6))]
+    for n, e in cases:
         rows, M = I.bunch(rng.integers(0, 60, n), 60)
-        cols, N = I.bunch(rng.integers(0, 9, n), 9)
+        if e is None:
+            cols, N = I.bunch(rng.integers(0, 9, n), 9)
+        else:
+            cols, N = np.arange(n // e), np.full(n // e, e, dtype=np.int32)
         u = I.haar_from_rng(rng, 60)
         A = np.ascontiguousarray(u[rows][:, cols])
         ref = oracle.perm_generalized(np.repeat(A, N, axis=1), M)
