@@ -109,7 +109,7 @@ def lib():
     if _lib is None:
         if not _LIB_PATH.exists():
             raise ImportError(f"{_LIB_PATH} is missing: build it with `python -m paper_2309_07027_amd.build` "
-                              "(or __graft_entry__.build()); there is no fallback path")
+                              "; there is no fallback path")
         # torch ships its own HIP runtime.  Loading it first makes libbbfg.so bind
         # to that same runtime (one HIP/HSA runtime per process); loading
         # libbbfg.so first would bring in a second runtime that torch cannot use.
