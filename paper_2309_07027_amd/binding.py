@@ -108,7 +108,7 @@ def lib():
     global _lib
     if _lib is None:
         if not _LIB_PATH.exists():
-            raise ImportError(f"{_LIB_PATH} is missing: build it with `python -m paper_2309_07027_amd.build` "
+            raise ImportError(f"{_LIB_PATH} is missing: build it with `python -m paper_2309_07027_amd.build`"
                               "; there is no fallback path")
         # torch ships its own HIP runtime.  Loading it first makes libbbfg.so bind
         # to that same runtime (one HIP/HSA runtime per process); loading

@@ -63,7 +63,7 @@ void synthetic_batch(int n, int cols, int count, uint64_t seed, std::vector<doub
 extern "C" {
 
 int bbfg_autotune(int32_t n_lo, int32_t n_hi, int32_t precision, const char* cache_path)
-{
+try {
     if (precision != BBFG_FP64 && precision != BBFG_FP32 && precision != BBFG_MINORS)
         return set_error(BBFG_EINVAL, "bad precision");
     const int kind = precision;
@@ -140,18 +140,20 @@ int bbfg_autotune(int32_t n_lo, int32_t n_hi, int32_t precision, const char* cac
     }
     return BBFG_OK;
 }
+BBFG_API_CATCH
 
 int bbfg_autotune_load(const char* cache_path)
-{
+try {
     if (!cache_path) return set_error(BBFG_EINVAL, "cache_path is NULL");
     Context* c = nullptr;
     BBFG_TRY(get_context(&c));
     std::lock_guard<std::recursive_mutex> lk(c->mu);
     return load_autotune_file(*c, cache_path);
 }
+BBFG_API_CATCH
 
 int bbfg_batch_unit_length(int32_t n_cols, int32_t precision, uint64_t* unit_length)
-{
+try {
     if (!unit_length) return set_error(BBFG_EINVAL, "unit_length is NULL");
     if (precision != BBFG_FP64 && precision != BBFG_FP32 && precision != BBFG_MINORS)
         return set_error(BBFG_EINVAL, "bad precision");
@@ -163,5 +165,6 @@ int bbfg_batch_unit_length(int32_t n_cols, int32_t precision, uint64_t* unit_len
     *unit_length = batch_unit_length(*c, n_cols, precision);
     return BBFG_OK;
 }
+BBFG_API_CATCH
 
 }  // extern "C"

@@ -68,13 +68,14 @@ const char* bbfg_last_error(void) { return last_error(); }
 int bbfg_version(void) { return BBFG_VERSION; }
 
 int bbfg_init(void)
-{
+try {
     Context* c = nullptr;
     return get_context(&c);
 }
+BBFG_API_CATCH
 
 int bbfg_set_cache_limits(uint64_t max_plans, uint64_t max_table_entries)
-{
+try {
     Context* c = nullptr;
     BBFG_TRY(get_context(&c));
     std::lock_guard<std::recursive_mutex> lk(c->mu);
@@ -82,6 +83,7 @@ int bbfg_set_cache_limits(uint64_t max_plans, uint64_t max_table_entries)
     c->table_entry_cap = max_table_entries ? (size_t)max_table_entries : (size_t(4) << 20);
     return BBFG_OK;
 }
+BBFG_API_CATCH
 
 int bbfg_set_stream(void* hip_stream)
 {
@@ -91,7 +93,7 @@ int bbfg_set_stream(void* hip_stream)
 
 int perm_bbfg(const bbfg_c128* A, int32_t n_rows, const int32_t* row_mult, int32_t n_cols, bbfg_c128* out,
               bbfg_info* info)
-{
+try {
     if (!out) return set_error(BBFG_EINVAL, "out is NULL");
     BBFG_TRY(validate_shape(row_mult, n_rows, n_cols, kMaxN));
     if (n_cols > 0 && !A) return set_error(BBFG_EINVAL, "A is NULL");
@@ -129,11 +131,12 @@ int perm_bbfg(const bbfg_c128* A, int32_t n_rows, const int32_t* row_mult, int32
     }
     return write_results(out, res, 1);
 }
+BBFG_API_CATCH
 
 int perm_batch(int32_t batch, const bbfg_c128* A_packed, const int64_t* A_offset, const int32_t* n_rows,
                const int32_t* row_mult_packed, const int64_t* row_mult_offset, const int32_t* n_cols,
                int32_t precision, bbfg_c128* out, double* rel_err_est)
-{
+try {
     if (batch < 0) return set_error(BBFG_EINVAL, "batch = %d < 0", batch);
     if (batch == 0) return BBFG_OK;
     if (!out || !A_offset || !n_rows || !row_mult_offset || !n_cols)
@@ -200,9 +203,10 @@ int perm_batch(int32_t batch, const bbfg_c128* A_packed, const int64_t* A_offset
         for (int32_t b = 0; b < batch; ++b) rel_err_est[b] = diag[2 * (size_t)b];
     return write_results(out, res.data(), (size_t)batch);
 }
+BBFG_API_CATCH
 
 int perm_minors(const bbfg_c128* A, int32_t n_rows, const int32_t* row_mult, int32_t n_cols, bbfg_c128* out)
-{
+try {
     if (!out) return set_error(BBFG_EINVAL, "out is NULL");
     if (n_cols < 1) return set_error(BBFG_EINVAL, "n_cols = %d < 1", n_cols);
     if (n_cols > kMaxN) return set_error(BBFG_ERANGE, "n_cols = %d exceeds the maximum %d", n_cols, kMaxN);
@@ -246,10 +250,11 @@ int perm_minors(const bbfg_c128* A, int32_t n_rows, const int32_t* row_mult, int
     }
     return write_results(out, res.data(), (size_t)n_cols);
 }
+BBFG_API_CATCH
 
 int perm_bbfg_cols(const bbfg_c128* A, int32_t n_rows, const int32_t* row_mult, int32_t n_cols, const int32_t* col_mult,
                    bbfg_c128* out, bbfg_info* info)
-{
+try {
     if (!out) return set_error(BBFG_EINVAL, "out is NULL");
     if (n_cols < 0) return set_error(BBFG_EINVAL, "n_cols = %d < 0", n_cols);
     if (n_cols > 0 && !col_mult) return set_error(BBFG_EINVAL, "col_mult is NULL");
@@ -317,13 +322,14 @@ int perm_bbfg_cols(const bbfg_c128* A, int32_t n_rows, const int32_t* row_mult, 
     }
     return write_results(out, res, 1);
 }
+BBFG_API_CATCH
 
 double perm_batch_last_kernel_ms(void) { return t_batch_kernel_ms; }
 
 int perm_batch_last_was_graph(void) { return t_batch_graph ? 1 : 0; }
 
 int bbfg_plan_query(const int32_t* row_mult, int32_t n_rows, int32_t n_cols, int32_t slots, bbfg_plan_summary* out)
-{
+try {
     if (!out) return set_error(BBFG_EINVAL, "out is NULL");
     BBFG_TRY(validate_shape(row_mult, n_rows, n_cols, kMaxN));
     if (slots < 0) return set_error(BBFG_EINVAL, "slots < 0");
@@ -353,10 +359,11 @@ int bbfg_plan_query(const int32_t* row_mult, int32_t n_rows, int32_t n_cols, int
     out->n_units = P.n == 0 ? 0 : P.units;
     return BBFG_OK;
 }
+BBFG_API_CATCH
 
 int bbfg_gray_table(const int32_t* radices, int32_t n_digits, int32_t max_len, int32_t* changed_digit,
                     int32_t* direction)
-{
+try {
     if (n_digits < 0 || n_digits > 64 || (n_digits > 0 && !radices) || !changed_digit || !direction)
         return set_error(BBFG_EINVAL, "bad arguments");
     uint64_t len = 1;
@@ -382,9 +389,10 @@ int bbfg_gray_table(const int32_t* radices, int32_t n_digits, int32_t max_len, i
     }
     return BBFG_OK;
 }
+BBFG_API_CATCH
 
 int bbfg_walk_occupancy(int32_t n_cols, int32_t precision, int32_t* waves_per_cu, int32_t* n_cu)
-{
+try {
     const int f32 = precision == BBFG_FP32 ? 1 : 0;
     if (n_cols < 1 || n_cols > (f32 ? kMaxNF32 : kMaxN)) return set_error(BBFG_ERANGE, "n_cols out of range");
     Context* c = nullptr;
@@ -396,5 +404,6 @@ int bbfg_walk_occupancy(int32_t n_cols, int32_t precision, int32_t* waves_per_cu
     if (n_cu) *n_cu = c->n_cu;
     return BBFG_OK;
 }
+BBFG_API_CATCH
 
 }  // extern "C"

@@ -5,6 +5,8 @@
 
 #include <cstdarg>
 #include <cstdint>
+#include <exception>
+#include <new>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -30,6 +32,13 @@ const char* last_error();
         hipError_t e_ = (expr);                                                                     \
         if (e_ != hipSuccess) return ::bbfg::set_error(BBFG_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
+
+// Catch clauses of the C entry points (function-try-blocks): no C++ exception
+// crosses the C ABI; a failed host allocation is BBFG_ENOMEM.
+#define BBFG_API_CATCH                                                                              \
+    catch (const std::bad_alloc&) { return ::bbfg::set_error(BBFG_ENOMEM, "host memory allocation failed"); } \
+    catch (const std::exception& e_) { return ::bbfg::set_error(BBFG_EDEVICE, "internal error: %s", e_.what()); } \
+    catch (...) { return ::bbfg::set_error(BBFG_EDEVICE, "internal error"); }
 
 #define BBFG_TRY(expr)            \
     do {                          \

@@ -292,7 +292,7 @@ using namespace bbfg;
 
 extern "C" int bs_sample(const bbfg_c128* U, int32_t m, const int32_t* input_occupation, int32_t n_samples,
                          double loss, uint64_t seed, int32_t* out_occupation, bbfg_info* info)
-{
+try {
     BBFG_TRY(cc_validate(U, m, input_occupation, n_samples, loss));
     if (n_samples > 0 && !out_occupation) return set_error(BBFG_EINVAL, "out_occupation is NULL");
     if (info) std::memset(info, 0, sizeof *info);
@@ -329,3 +329,4 @@ extern "C" int bs_sample(const bbfg_c128* U, int32_t m, const int32_t* input_occ
     }
     return BBFG_OK;
 }
+BBFG_API_CATCH

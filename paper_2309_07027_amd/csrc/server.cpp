@@ -75,6 +75,7 @@ struct bbfg_server {
     std::string init_message;
 
     void run();
+    void run_guarded();
     void fail_active(int code, const std::string& msg);
 };
 
@@ -93,6 +94,34 @@ void bbfg_server::fail_active(int code, const std::string& msg)
         --outstanding;
     }
     active.clear();
+    cv_done.notify_all();
+}
+
+// The worker's entry: an exception (a failed host allocation) stops the worker
+// and fails every job it holds; later submissions are refused.
+void bbfg_server::run_guarded()
+{
+    int code = BBFG_OK;
+    try {
+        run();
+        return;
+    } catch (const std::bad_alloc&) {
+        code = BBFG_ENOMEM;
+    } catch (...) {
+        code = BBFG_EDEVICE;
+    }
+    fail_active(code, "server worker stopped");
+    std::lock_guard<std::mutex> lk(mu);
+    init_error = code;
+    init_message = "server worker stopped";
+    for (auto& j : queue) {
+        j->state = 3;
+        j->err_code = code;
+        j->err = init_message;
+        j->t_done = Clock::now();
+        --outstanding;
+    }
+    queue.clear();
     cv_done.notify_all();
 }
 
@@ -241,7 +270,7 @@ void bbfg_server::run()
 extern "C" {
 
 int bs_server_create(size_t hbm_budget_bytes, int32_t max_active_jobs, bbfg_server** srv)
-{
+try {
     if (!srv) return set_error(BBFG_EINVAL, "srv is NULL");
     if (max_active_jobs < 1) return set_error(BBFG_EINVAL, "max_active_jobs < 1");
     Context* c = nullptr;
@@ -258,14 +287,15 @@ int bs_server_create(size_t hbm_budget_bytes, int32_t max_active_jobs, bbfg_serv
     s->budget = hbm_budget_bytes;
     BBFG_HIP(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
     bbfg_server* raw = s.get();
-    s->worker = std::thread([raw] { raw->run(); });
+    s->worker = std::thread([raw] { raw->run_guarded(); });
     *srv = s.release();
     return BBFG_OK;
 }
+BBFG_API_CATCH
 
 int bs_server_submit(bbfg_server* srv, const bbfg_c128* U, int32_t m, const int32_t* input_occupation,
                      int32_t n_samples, double loss, uint64_t seed, uint64_t* job_id)
-{
+try {
     if (!srv || !job_id) return set_error(BBFG_EINVAL, "NULL argument");
     BBFG_TRY(cc_validate(U, m, input_occupation, n_samples, loss));
     auto j = std::make_shared<SJob>();
@@ -285,6 +315,7 @@ int bs_server_submit(bbfg_server* srv, const bbfg_c128* U, int32_t m, const int3
     j->footprint = cc_job_footprint(m, n, n_samples, loss);
     j->t_submit = Clock::now();
     std::lock_guard<std::mutex> lk(srv->mu);
+    if (srv->init_error != BBFG_OK) return set_error(srv->init_error, "%s", srv->init_message.c_str());
     j->id = srv->next_id++;
     srv->jobs[j->id] = j;
     srv->queue.push_back(j);
@@ -295,9 +326,10 @@ int bs_server_submit(bbfg_server* srv, const bbfg_c128* U, int32_t m, const int3
     srv->cv_work.notify_one();
     return BBFG_OK;
 }
+BBFG_API_CATCH
 
 int bs_server_poll(bbfg_server* srv, uint64_t job_id, int32_t* out_occupation, double* latency_s)
-{
+try {
     if (!srv) return set_error(BBFG_EINVAL, "srv is NULL");
     std::lock_guard<std::mutex> lk(srv->mu);
     auto it = srv->jobs.find(job_id);
@@ -314,25 +346,28 @@ int bs_server_poll(bbfg_server* srv, uint64_t job_id, int32_t* out_occupation, d
     srv->jobs.erase(it);
     return BBFG_OK;
 }
+BBFG_API_CATCH
 
 int bs_server_drain(bbfg_server* srv)
-{
+try {
     if (!srv) return set_error(BBFG_EINVAL, "srv is NULL");
     std::unique_lock<std::mutex> lk(srv->mu);
     srv->cv_done.wait(lk, [srv] { return srv->outstanding == 0; });
     return BBFG_OK;
 }
+BBFG_API_CATCH
 
 int bs_server_stats(bbfg_server* srv, bbfg_server_stats* out)
-{
+try {
     if (!srv || !out) return set_error(BBFG_EINVAL, "NULL argument");
     std::lock_guard<std::mutex> lk(srv->mu);
     *out = srv->st;
     return BBFG_OK;
 }
+BBFG_API_CATCH
 
 int bs_server_destroy(bbfg_server* srv)
-{
+try {
     if (!srv) return set_error(BBFG_EINVAL, "srv is NULL");
     {
         std::lock_guard<std::mutex> lk(srv->mu);
@@ -344,5 +379,6 @@ int bs_server_destroy(bbfg_server* srv)
     delete srv;
     return BBFG_OK;
 }
+BBFG_API_CATCH
 
 }  // extern "C"
