@@ -218,7 +218,8 @@ int perm_batch_last_was_graph(void);
  * function of the column count only, so an item's result does not depend on the
  * other items of the batch.  L is chosen by an autotuner that times synthetic
  * batches of n-photon permanents (photons at random on 60 modes) for
- * L in {64, ..., 4096} on the current device; untuned n use L = 512.  The
+ * L in {64, ..., 4096} on the current device and keeps the longest L within 2 %
+ * of the best rate (the shortest for BBFG_MINORS); untuned n use L = 512.  The
  * leave-one-column-out walks of the sampler (precision BBFG_MINORS; n = the
  * size of the minors, n + 1 columns) are tuned separately: a unit of theirs
  * ends with one reduction per target column.

@@ -6,7 +6,8 @@
 // depends on the column count n (seeding costs O(r n), a step O(n)), so it is
 // tuned per n: a synthetic batch of n-photon permanents (photons placed at
 // random on 60 modes, as in the sampling workloads) is timed for each
-// candidate L and the fastest per addend is kept.  Untuned n use a default.
+// candidate L and, among those within 2 % of the fastest per addend, the
+// longest is kept (the shortest for the minors kind).  Untuned n use a default.
 // The leave-one-column-out walks of the sampler (kind BBFG_MINORS) end every
 // unit with one reduction per target column, so they are tuned on their own.
 #include <algorithm>
@@ -87,10 +88,10 @@ try {
         BBFG_TRY(dA.ensure(sizeof(double) * A.size()));
         BBFG_HIP(hipMemcpyAsync(dA.p, A.data(), sizeof(double) * A.size(), hipMemcpyHostToDevice, s));
         BBFG_HIP(hipStreamSynchronize(s));
-        double best_rate = -1.0;
-        uint64_t best_L = kDefaultBatchUnit;
+        std::vector<std::pair<uint64_t, double>> rates;  // (L, addends per ms)
         for (uint64_t L : kCandidates) {
             c->batch_L[std::make_pair(n, kind)] = L;
+            ++c->plan_epoch;
             std::vector<PermItem> items;
             std::deque<std::vector<int32_t>> keep;
             std::vector<uint32_t> slot((size_t)cols);
@@ -122,13 +123,22 @@ try {
                 BBFG_TRY(run_perms(*c, items, f32, false, nullptr, nullptr, &rr));
                 ms_best = std::min(ms_best, rr.kernel_ms);
             }
-            const double rate = (double)addends / ms_best;
-            if (rate > best_rate * 1.02) {  // prefer shorter units unless a longer one is clearly faster
-                best_rate = rate;
-                best_L = L;
-            }
+            rates.push_back({L, (double)addends / ms_best});
         }
+        // Within 2 % of the best rate: plain batches take the longest unit (fewer
+        // units, less per-unit reduction), the sampler's minors the shortest (its
+        // steps are often small, and short units spread them over the device).
+        double best_rate = 0.0;
+        for (auto& r : rates) best_rate = std::max(best_rate, r.second);
+        uint64_t best_L = kDefaultBatchUnit;
+        bool found = false;
+        for (auto& r : rates)
+            if (r.second >= 0.98 * best_rate && (!found || (minors ? r.first < best_L : r.first > best_L))) {
+                best_L = r.first;
+                found = true;
+            }
         c->batch_L[std::make_pair(n, kind)] = best_L;
+        ++c->plan_epoch;
         dA.release();
     }
     if (cache_path) {

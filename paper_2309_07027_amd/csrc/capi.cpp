@@ -167,6 +167,16 @@ try {
         std::lock_guard<std::recursive_mutex> lk(c->mu);
         const double* Ad = nullptr;
         BBFG_TRY(device_view(*c, A_packed, extent, &Ad));
+        // same shapes and multiplicities as the last batch (and unchanged unit
+        // lengths): its plans are reused
+        Context::BatchMemo& memo = c->batch_memo;
+        std::vector<int32_t> flat;
+        for (int32_t b = 0; b < batch; ++b)
+            if (n_cols[b] > 0) flat.insert(flat.end(), row_mult_packed + row_mult_offset[b],
+                                           row_mult_packed + row_mult_offset[b] + n_rows[b]);
+        const bool hit = memo.epoch == c->plan_epoch && memo.f32 == f32 && memo.n_rows.size() == (size_t)batch &&
+                         std::equal(memo.n_rows.begin(), memo.n_rows.end(), n_rows) &&
+                         std::equal(memo.n_cols.begin(), memo.n_cols.end(), n_cols) && memo.mult == flat;
         std::vector<PermItem> items;
         std::vector<int32_t> idx;
         items.reserve((size_t)batch);
@@ -179,9 +189,19 @@ try {
             it.n_rows = n_rows[b];
             it.n = n_cols[b];
             it.mult = row_mult_packed + row_mult_offset[b];
-            BBFG_TRY(get_plan(*c, it.mult, it.n_rows, it.n, f32, PLAN_BATCH, &it.plan));
+            if (hit) it.plan = memo.plans[items.size()];
+            else BBFG_TRY(get_plan(*c, it.mult, it.n_rows, it.n, f32, PLAN_BATCH, &it.plan));
             items.push_back(std::move(it));
             idx.push_back(b);
+        }
+        if (!hit) {
+            memo.epoch = c->plan_epoch;
+            memo.f32 = f32;
+            memo.n_rows.assign(n_rows, n_rows + batch);
+            memo.n_cols.assign(n_cols, n_cols + batch);
+            memo.mult.swap(flat);
+            memo.plans.clear();
+            for (auto& it : items) memo.plans.push_back(it.plan);
         }
         std::vector<double> r2(2 * items.size()), d2(2 * items.size());
         RunResult rr;

@@ -213,6 +213,7 @@ int load_autotune_file(Context& c, const char* path)
         if (n >= 1 && n <= kMaxN && L >= 1 && (prec == BBFG_FP64 || prec == BBFG_FP32 || prec == BBFG_MINORS)) {
             c.batch_L[std::make_pair(n, prec)] = (uint64_t)L;
             ++count;
+            ++c.plan_epoch;
         }
     }
     std::fclose(f);
@@ -362,12 +363,13 @@ int run_perms(Context& c, Workspace& w, std::vector<PermItem>& items, int f32, b
     std::vector<size_t> order(nitem);
     std::iota(order.begin(), order.end(), 0);
     if (!single) {
-        auto cost = [&](size_t i) {
+        std::vector<double> cost(nitem);
+        for (size_t i = 0; i < nitem; ++i) {
             const HostPlan& p = *items[i].plan;
             const double nc = cols_of(items[i]);
-            return (double)p.span / (double)p.units_per_group * (6.0 * nc - 2.0 + 12.0 * items[i].targets);
-        };
-        std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return cost(x) > cost(y); });
+            cost[i] = (double)p.span / (double)p.units_per_group * (6.0 * nc - 2.0 + 12.0 * items[i].targets);
+        }
+        std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return cost[x] > cost[y]; });
     }
     std::vector<uint64_t> unit_base(nitem), part_base(nitem);
     uint64_t total_units = 0, total_parts = 0;

@@ -138,6 +138,15 @@ struct Context {
     size_t table_entry_cap = size_t(4) << 20;  // cached table entries (16 B each) before a flush
     PlanParams params;
     std::map<std::pair<int, int>, uint64_t> batch_L;  // (n, kind) -> tuned unit length
+    uint64_t plan_epoch = 0;  // bumped when unit lengths change (plans of earlier calls are stale)
+    // the shapes and plans of the last perm_batch: a batch with the same shapes
+    // and multiplicities reuses its plans without a lookup per item
+    struct BatchMemo {
+        uint64_t epoch = ~0ull;
+        int f32 = -1;
+        std::vector<int32_t> n_rows, n_cols, mult;
+        std::vector<std::shared_ptr<const HostPlan>> plans;
+    } batch_memo;
     // captured batch evaluations, keyed by layout (replayed on repeats)
     std::unordered_map<uint64_t, hipGraphExec_t> graphs;
     std::unordered_set<uint64_t> graph_seen;
