@@ -210,7 +210,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-log2", type=int, default=25)
+    ap.add_argument("--cpu-sample-log2", type=int, default=28,
+                    help="oracle baseline sample: the first 2^k addends of case (a) (k = 28: ~15 s on 16 cores)")
     ap.add_argument("--serve-jobs", type=int, default=128)
     ap.add_argument("--batch-reps", type=int, default=10)
     ap.add_argument("--no-serving", action="store_true")

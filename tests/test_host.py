@@ -3,6 +3,7 @@ exports every entry point of include/bbfg.h, arguments are validated before any
 device work, and the planner's n-ary Gray code and work split are right."""
 import itertools
 import math
+import os
 import re
 from pathlib import Path
 
@@ -178,3 +179,13 @@ def test_plan_c2_workloads():
     assert s["n_addends"] == 2 ** 29 and s["n_units"] == 3072 and s["lane_product"] == 64
     s = B.plan_query(*(lambda AM: (AM[1], AM[0].shape[1]))(I.c2b()), slots=3072)
     assert s["n_addends"] == 3 * 4 ** 9 and s["lane_product"] == 64
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU; asking for more exits with a message (no GPU work)."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    p = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120, cwd=root)
+    assert p.returncode != 0 and "one GPU" in p.stderr
