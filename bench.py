@@ -217,7 +217,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--large-samples", type=int, default=2, help="samples per n = 40 run (0 = skip)")
+    ap.add_argument("--large-samples", type=int, default=10, help="samples per n = 40 run (0 = skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run one plain device-to-device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
