@@ -15,6 +15,7 @@
 // the item's shape), so they are bitwise identical to bs_sample's.
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -47,6 +48,8 @@ struct SJob {
     std::string err;
     std::unique_ptr<CCJob> cc;
     std::vector<int32_t> out;
+    int half = 0;        // pipeline half that advances this job's samples
+    double weight = 0;   // its share of a half's work (for balancing)
 };
 
 }  // namespace
@@ -125,11 +128,12 @@ void bbfg_server::run_guarded()
     cv_done.notify_all();
 }
 
-// The samples of every active job are split between two halves (sample s of a
-// job goes to half s % 2).  The halves alternate: while the device runs one
-// half's step, the worker applies the other half's draws, retires finished
-// jobs, admits new ones and queues that half's next step, so the device does
-// not wait for the host between steps.  Each half has its own workspace.
+// Every active job belongs to one of two halves (a new job joins the half with
+// less work; a lone job thus runs full-size steps).  The halves alternate:
+// while the device runs one half's step, the worker applies the other half's
+// draws, retires finished jobs, admits new ones and queues that half's next
+// step, so the device does not wait for the host between steps.  Each half has
+// its own workspace.
 void bbfg_server::run()
 {
     (void)hipSetDevice(device);
@@ -140,6 +144,7 @@ void bbfg_server::run()
         CCPending pend;
     };
     Half half[2];
+    double half_work[2] = {0.0, 0.0};  // weights of the active jobs of each half
     for (Half& h : half) {
         const int rc = h.ws.init();
         if (rc != BBFG_OK) {
@@ -165,6 +170,7 @@ void bbfg_server::run()
         if (rc != BBFG_OK) {
             half[0].pend.queued = half[1].pend.queued = false;
             fail_active(rc, last_error());
+            half_work[0] = half_work[1] = 0.0;
             continue;
         }
         // 2. retire finished jobs, admit queued ones (or sleep when idle)
@@ -180,6 +186,7 @@ void bbfg_server::run()
                 }
                 j->out = j->cc->out;
                 spare.push_back(std::move(j->cc));
+                half_work[j->half] -= j->weight;
                 j->state = 2;
                 j->t_done = Clock::now();
                 used -= j->footprint;
@@ -236,14 +243,20 @@ void bbfg_server::run()
                                  j->seed, true);
                 if (rc != BBFG_OK) break;
                 for (int s = 0; s < j->n_samples; ++s) cc_start_sample(*j->cc, s);
+                // work ~ samples x the addends of the last (largest) steps
+                j->weight = (double)j->n_samples * std::ldexp(1.0, std::min(j->cc->n, 60));
+                j->half = half_work[1] < half_work[0] ? 1 : 0;
+                half_work[j->half] += j->weight;
                 std::lock_guard<std::mutex> lk(mu);
                 active.push_back(j);
             }
             if (rc == BBFG_OK) {
                 h.act.clear();
                 for (auto& j : active)
-                    for (int s = which; s < j->n_samples; s += 2)
-                        if (j->cc->n > 0 && j->cc->samples[(size_t)s].k <= j->cc->n) h.act.push_back({j->cc.get(), s});
+                    if (j->half == which)
+                        for (int s = 0; s < j->n_samples; ++s)
+                            if (j->cc->n > 0 && j->cc->samples[(size_t)s].k <= j->cc->n)
+                                h.act.push_back({j->cc.get(), s});
                 if (!h.act.empty()) rc = cc_step_begin(*ctx, h.ws, h.act, h.pend, nullptr);
             }
         }
@@ -255,6 +268,7 @@ void bbfg_server::run()
             }
             half[0].pend.queued = half[1].pend.queued = false;
             fail_active(rc, last_error());
+            half_work[0] = half_work[1] = 0.0;
             continue;
         }
         {
