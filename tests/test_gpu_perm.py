@@ -423,3 +423,42 @@ def test_column_multiplicities_edges():
         B.perm_bbfg_cols(A, [2, 1], [2, 2, -1])
     with pytest.raises(B.BBFGError):
         B.perm_bbfg_cols(np.ones((1, 1), dtype=np.complex128), [49], [49])  # beyond BBFG_MAX_N
+
+
+def test_batch_ragged_and_empty_items(oracle):
+    """A batch mixing empty permanents (n = 0 -> 1), single columns, zero
+    multiplicities, the largest FP64 size (n = 48, its own bucket) and ordinary
+    items; every value against the oracle (closed form for n = 48)."""
+    rng = np.random.default_rng(909)
+    mats = [(np.zeros((0, 0), dtype=np.complex128), np.zeros(0, dtype=np.int32)),
+            (rng.standard_normal((1, 1)) + 1j * rng.standard_normal((1, 1)), np.array([1], dtype=np.int32)),
+            (rng.standard_normal((3, 4)) + 1j * rng.standard_normal((3, 4)), np.array([2, 0, 2], dtype=np.int32)),
+            (np.zeros((2, 0), dtype=np.complex128), np.array([0, 0], dtype=np.int32))]
+    mats += [rand_instance(rng, n, "random") for n in (5, 13, 22)]
+    mats.append((np.ones((8, 48), dtype=np.complex128) / 48, np.full(8, 6, dtype=np.int32)))  # perm = 48!/48^48
+    out, err = B.perm_batch(mats, with_err=True)
+    assert out[0] == 1 and out[3] == 1
+    for i in (1, 2, 4, 5, 6):
+        A, M = mats[i]
+        assert rel(out[i], oracle.perm_generalized(A, M)) <= TOL, i
+    ref48 = math.exp(math.lgamma(49) - 48 * math.log(48))
+    assert abs(out[7] - ref48) / ref48 <= max(TOL, err[7])
+
+
+def test_c3_batch_after_autotuning_vs_golden(golden):
+    """The 4096-item batch as bench.py times it: unit lengths tuned on this
+    device first, then FP64 and FP32 against the oracle's sampled items."""
+    B.autotune(8, 24)
+    B.autotune(8, 24, precision=B.BBFG_FP32)
+    items = I.c3(4096)
+    idx = [int(k.split("_")[1]) for k in golden if k.startswith("c3_")]
+    for i in idx:
+        A, M, _, _ = golden[f"c3_{i}"]
+        items[i] = (A, M)
+    say("case c3 4096 items after autotuning")
+    out = B.perm_batch(items)
+    out32 = B.perm_batch(items, precision=B.BBFG_FP32)
+    for i in idx:
+        ref = golden[f"c3_{i}"][2]
+        assert rel(out[i], ref) <= TOL, i
+        assert rel(out32[i], ref) < 1e-2, i
