@@ -282,9 +282,12 @@ def main():
                        "kappa": info["kappa"], "value": [v.real, v.imag]}
     dom = per_case["a"]
     achieved = dom["kernel_tflops"]
+    fma_tflops, _ = B.fp64_fma_peak()  # measured FMA rate of this device, for context
     roofline = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": measured_traffic(),
                 "kernel": "walk_single_kernel<30,double> (case a)",
+                "measured_fp64_fma_tflops": round(fma_tflops, 2),
+                "frac_of_measured_fma": round(achieved / fma_tflops, 4),
                 "flops_per_launch": dom["flops"], "avg_launch_ms": dom["kernel_ms"]}
     out = {"metric": METRIC, "value": round(value, 3), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,

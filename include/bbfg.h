@@ -338,6 +338,14 @@ int bbfg_plan_query(const int32_t *row_mult, int32_t n_rows, int32_t n_cols, int
 int bbfg_gray_table(const int32_t *radices, int32_t n_digits, int32_t max_len,
                     int32_t *changed_digit, int32_t *direction);
 
+/* Measured FP64 fused multiply-add throughput of the device (TFLOP/s, an FMA
+ * counted as 2 flops): independent FMA chains in 32 wavefronts per compute unit,
+ * about 10 ms of warm-up then about 40 ms timed; *ms (nullable) is the timed
+ * kernel's duration.  The walk
+ * kernels' rates are quoted against the published peak and against this.
+ * Errors: BBFG_EINVAL, BBFG_EDEVICE. */
+int bbfg_fp64_fma_peak(double *tflops, double *ms);
+
 /* Resident wavefronts per compute unit of the walk kernel for n_cols columns
  * and the number of compute units (device query).  Errors: BBFG_EDEVICE. */
 int bbfg_walk_occupancy(int32_t n_cols, int32_t precision, int32_t *waves_per_cu, int32_t *n_cu);

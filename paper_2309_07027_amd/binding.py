@@ -95,6 +95,7 @@ SIGNATURES = {
     "bbfg_plan_query": (ctypes.c_int, [_PI32, _I32, _I32, _I32, ctypes.POINTER(PlanSummary)]),
     "bbfg_gray_table": (ctypes.c_int, [_PI32, _I32, _I32, _PI32, _PI32]),
     "bbfg_walk_occupancy": (ctypes.c_int, [_I32, _I32, _PI32, _PI32]),
+    "bbfg_fp64_fma_peak": (ctypes.c_int, [_PD, _PD]),
     "bbfg_autotune": (ctypes.c_int, [_I32, _I32, _I32, ctypes.c_char_p]),
     "bbfg_autotune_load": (ctypes.c_int, [ctypes.c_char_p]),
     "bbfg_batch_unit_length": (ctypes.c_int, [_I32, _I32, ctypes.POINTER(ctypes.c_uint64)]),
@@ -364,6 +365,14 @@ def batch_unit_length(n_cols: int, precision: int = BBFG_FP64) -> int:
     L = ctypes.c_uint64()
     _check(lib().bbfg_batch_unit_length(int(n_cols), int(precision), ctypes.byref(L)))
     return L.value
+
+
+def fp64_fma_peak():
+    """(TFLOP/s, ms) of the device's measured FP64 FMA throughput."""
+    t = ctypes.c_double()
+    ms = ctypes.c_double()
+    _check(lib().bbfg_fp64_fma_peak(ctypes.byref(t), ctypes.byref(ms)))
+    return t.value, ms.value
 
 
 def walk_occupancy(n_cols: int, precision: int = BBFG_FP64):

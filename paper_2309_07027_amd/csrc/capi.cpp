@@ -411,6 +411,30 @@ try {
 }
 BBFG_API_CATCH
 
+int bbfg_fp64_fma_peak(double* tflops, double* ms)
+try {
+    if (!tflops) return set_error(BBFG_EINVAL, "tflops is NULL");
+    Context* c = nullptr;
+    BBFG_TRY(get_context(&c));
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    hipStream_t s = current_stream();
+    const uint32_t blocks = 8u * (uint32_t)c->n_cu;  // 32 wavefronts per compute unit
+    DevBuf out;
+    BBFG_TRY(out.ensure(sizeof(double) * 256 * (size_t)blocks));
+    double flops = 0.0;
+    BBFG_HIP(launch_fma_peak(blocks, 65536, out.as<double>(), s, &flops));  // warm-up: clocks ramp
+    BBFG_HIP(hipEventRecord(c->ws.ev0, s));
+    BBFG_HIP(launch_fma_peak(blocks, 262144, out.as<double>(), s, &flops));
+    BBFG_HIP(hipEventRecord(c->ws.ev1, s));
+    BBFG_HIP(hipStreamSynchronize(s));
+    float t = 0.f;
+    BBFG_HIP(hipEventElapsedTime(&t, c->ws.ev0, c->ws.ev1));
+    *tflops = flops / ((double)t * 1e-3) / 1e12;
+    if (ms) *ms = t;
+    return BBFG_OK;
+}
+BBFG_API_CATCH
+
 int bbfg_walk_occupancy(int32_t n_cols, int32_t precision, int32_t* waves_per_cu, int32_t* n_cu)
 try {
     const int f32 = precision == BBFG_FP32 ? 1 : 0;

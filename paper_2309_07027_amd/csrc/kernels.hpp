@@ -35,5 +35,7 @@ hipError_t launch_prep(uint32_t items, hipStream_t s, const PrepItem* it, const 
 hipError_t launch_finalize(uint32_t results, hipStream_t s, const PermDesc* descs, const uint32_t* res_item,
                            const double* partials, double* out, double* diag);
 hipError_t launch_init_binom(double* tab, hipStream_t s);
+// FP64 FMA throughput probe over `blocks` blocks of 256 lanes; *flops = the work
+hipError_t launch_fma_peak(uint32_t blocks, uint32_t iters, double* out, hipStream_t s, double* flops);
 
 }  // namespace bbfg
