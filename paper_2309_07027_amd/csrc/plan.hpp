@@ -16,7 +16,7 @@ struct PlanParams {
     uint32_t q_max_heavy = 512;  // largest Gray block length when some M'_k > 3
     // single launches: units fill every resident wavefront slot when the sum allows
     uint64_t l_floor = 16;     // shortest unit (positions per lane) of a single launch
-    uint64_t l_target = 4096;  // unit length of sums larger than one round of slots
+    uint64_t l_target = 1024;  // unit length of sums larger than one round of slots
     // batched launches: units of a fixed length, so an item's split depends on its
     // own shape only (0 = use the single-launch rule)
     uint64_t l_batch = 0;
