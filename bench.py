@@ -43,9 +43,11 @@ sys.path.insert(0, ROOT)
 METRIC = "FP64 GFLOP/s (% of peak) for n=30 perm; BS samples/s + p99 latency, m=60"
 FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector: 256 CU x 128 flop/clk x 2.4 GHz
 CASES = ("a", "b", "c")
-# sources of the case-(a) walk kernel: its counter summary is void once they change
+# sources of the case-(a) walk kernel and of its work split: its counter summary
+# is void once they change
 KERNEL_SOURCES = ("paper_2309_07027_amd/csrc/walk_core.hpp", "paper_2309_07027_amd/csrc/walk.hip",
-                  "paper_2309_07027_amd/csrc/walk_device.hpp", "paper_2309_07027_amd/csrc/internal.hpp")
+                  "paper_2309_07027_amd/csrc/walk_device.hpp", "paper_2309_07027_amd/csrc/internal.hpp",
+                  "paper_2309_07027_amd/csrc/plan.hpp", "paper_2309_07027_amd/csrc/plan.cpp")
 
 
 def flops(n, M, cprime):
