@@ -2,7 +2,7 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
                     [--serve-jobs J] [--no-serving] [--no-batch] [--no-autotune]
-                    [--large-samples S]
+                    [--large-samples S] [--no-t0-fit]
 
 Headline workload (synthetic, seeded): the three single n = 30 generalized
 permanents of a 60 x 60 Haar unitary (seed 0):
@@ -23,7 +23,10 @@ Also reported on the same line:
             at once through the continuous-batching server (capacity), and
             Poisson arrivals at fractions of that capacity (p50 / p99 latency);
   large   : 40-photon sampling on 60 modes, ideal and with transmission 0.5
-            (120 x 120 dilation), seconds per sample.
+            (120 x 120 dilation), seconds per sample;
+  T0 fit  : seconds per sample at n = 30 ... 40 photons (ideal, 30 % and 50 %
+            loss) fitted with the single constant T0 of the paper's
+            sampling-time model (Eq. performance), the paper's portable figure.
 
 Prints ONE JSON line.  The dominant kernel's roofline uses the walk kernel's
 own device time, measured with HIP events on the stream it runs on.
@@ -33,6 +36,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -90,9 +94,27 @@ def cpu_baseline(sample_terms: int):
     O.perm_glynn_gray(A, first=0, count=sample_terms)
     dt = time.perf_counter() - t0
     gflops = sample_terms * (8 * 30 - 4) / dt / 1e9
+    # the same oracle on one thread, over a 1/32 sample
+    one = max(1, sample_terms >> 5)
+    O.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        O.perm_glynn_gray(A, first=0, count=one)
+        dt1 = time.perf_counter() - t0
+    finally:
+        O.set_threads(threads)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": round(gflops, 4), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
             "sample": f"case (a) n=30: addends [0, {sample_terms}) of 2^29 (Gray-coded Eq. bbfg in "
-                      f"double-double), {dt:.2f} s; GFLOP/s at the same 8n-4 flops per addend"}
+                      f"double-double), {dt:.2f} s; GFLOP/s at the same 8n-4 flops per addend",
+            "single_thread": {"value": round(one * (8 * 30 - 4) / dt1 / 1e9, 4), "unit": "GFLOP/s",
+                              "seconds": round(dt1, 2), "sample": f"addends [0, {one})"},
+            "cpu_model": model}
 
 
 def batch_section(B, I, torch, np, reps: int):
@@ -206,6 +228,60 @@ def large_sampling_section(B, I, samples: int):
     return out
 
 
+def cc_cost_model(n: int, m: int) -> float:
+    """Average-case cost of one Clifford & Clifford sample of n photons on m modes in
+    units of T0 (Eq. performance, Sec. 4): n(m+n)/m * C(2m+n, n+1) / C(m+n, n+1) + n^2 m."""
+    return n * (m + n) / m * math.comb(2 * m + n, n + 1) / math.comb(m + n, n + 1) + n * n * m
+
+
+def fit_t0(points) -> float:
+    """The single parameter T0 of Eq. performance over (n, modes, s_per_sample) points:
+    least squares on log(time), i.e. the geometric mean of time / model."""
+    return math.exp(sum(math.log(t / cc_cost_model(n, mm)) for n, mm, t in points) / len(points))
+
+
+# photon counts and samples per point of the T0 fit (about 20 s of sampling)
+T0_FIT_PLAN = {0.0: ((30, 64), (32, 64), (34, 64), (36, 32), (38, 16)),
+               0.3: ((30, 32), (32, 32), (34, 32), (36, 16), (38, 6)),
+               0.5: ((30, 32), (32, 32), (34, 32), (36, 16), (38, 6))}
+
+
+def t0_fit_section(B, I, np, large):
+    """Fit T0 of Eq. performance to this device's seconds per sample on 60 modes (Haar
+    seed 5, photons in the first n modes): ideal, 30 % and 50 % loss, the lossy cases
+    priced at the 2m = 120 modes of the dilation. The n = 40 runs of the large-sampling
+    section join the fit when present. The paper's fit over its three sets: 7.5e-11 s."""
+    u = I.haar_unitary(5)
+    sets = {}
+    for loss, plan in T0_FIT_PLAN.items():
+        mm = 60 if loss == 0.0 else 120
+        pts = []
+        for n, samples in plan:
+            occ = np.zeros(60, dtype=np.int32)
+            occ[:n] = 1
+            B.bs_sample(u, occ, 1, loss, 1)  # plans and tables of this size
+            t = time.perf_counter()
+            B.bs_sample(u, occ, samples, loss, 100 + n)
+            pts.append((n, mm, (time.perf_counter() - t) / samples, samples))
+        sets[loss] = pts
+    if large:
+        sets[0.0].append((40, 60, large["ideal"]["s_per_sample"], large["samples"]))
+        sets[0.5].append((40, 120, large["lossy_0.5"]["s_per_sample"], large["samples"]))
+    out = {"modes": 60, "model": "Eq. performance; lossy sets priced at 2m = 120 modes",
+           "paper_t0_s": 7.5e-11, "sets": {}}
+    every = []
+    for loss, pts in sets.items():
+        tri = [(n, mm, t) for n, mm, t, _ in pts]
+        every += tri
+        out["sets"][f"loss_{loss}"] = {
+            "t0_s": float(f"{fit_t0(tri):.4g}"),
+            "points": [{"n": n, "samples": k, "s_per_sample": float(f"{t:.4g}"),
+                        "model_t0_units": float(f"{cc_cost_model(n, mm):.4g}")} for n, mm, t, k in pts]}
+    out["t0_s"] = float(f"{fit_t0(every):.4g}")
+    out["paper_t0_over_ours"] = round(7.5e-11 / out["t0_s"], 1)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -220,6 +296,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--large-samples", type=int, default=10, help="samples per n = 40 run (0 = skip)")
+    ap.add_argument("--no-t0-fit", action="store_true", help="skip the sampling-time model fit")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run one plain device-to-device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
@@ -319,6 +396,8 @@ def main():
         out["bs_p99_at_load"] = near["load"]
     if args.large_samples > 0:
         out["large_sampling"] = large_sampling_section(B, I, args.large_samples)
+    if not args.no_t0_fit:
+        out["sampling_t0_fit"] = t0_fit_section(B, I, np, out.get("large_sampling"))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(1 << args.cpu_sample_log2)
     print(json.dumps(out), flush=True)

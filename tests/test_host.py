@@ -189,3 +189,17 @@ def test_bench_refuses_more_than_one_gpu():
     p = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120, cwd=root)
     assert p.returncode != 0 and "one GPU" in p.stderr
+
+
+def test_sampling_cost_model_and_t0_fit():
+    """Eq. performance at the paper's fitted T0 and 40 photons on 60 modes is about a
+    minute per sample (the paper measured about 80 s); the fit recovers T0 exactly from
+    model-generated times."""
+    import bench
+    from math import comb
+    n, m = 40, 60
+    direct = n * (m + n) / m * comb(2 * m + n, n + 1) / comb(m + n, n + 1) + n * n * m
+    assert bench.cc_cost_model(n, m) == pytest.approx(direct, rel=1e-15)
+    assert 50 < 7.5e-11 * bench.cc_cost_model(40, 60) < 80
+    pts = [(k, mm, 3.1e-13 * bench.cc_cost_model(k, mm)) for k in (30, 34, 38) for mm in (60, 120)]
+    assert bench.fit_t0(pts) == pytest.approx(3.1e-13, rel=1e-12)
