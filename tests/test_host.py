@@ -203,3 +203,17 @@ def test_sampling_cost_model_and_t0_fit():
     assert 50 < 7.5e-11 * bench.cc_cost_model(40, 60) < 80
     pts = [(k, mm, 3.1e-13 * bench.cc_cost_model(k, mm)) for k in (30, 34, 38) for mm in (60, 120)]
     assert bench.fit_t0(pts) == pytest.approx(3.1e-13, rel=1e-12)
+
+
+def test_cpu_baseline_contract():
+    """bench.py's cpu_baseline: the oracle timed as is, on all threads and on one,
+    reported with the fields the bench line carries (tiny sample, CPU only)."""
+    import bench
+    cb = bench.cpu_baseline(1 << 12)
+    assert cb["kind"] == "oracle" and cb["unit"] == "GFLOP/s"
+    assert cb["value"] > 0 and cb["cores"] >= 1
+    assert "addends [0, 4096)" in cb["sample"]
+    st = cb["single_thread"]
+    assert st["value"] > 0 and st["unit"] == "GFLOP/s" and "addends [0, 128)" in st["sample"]
+    from oracle import oracle as O
+    assert O.get_threads() == cb["cores"]  # thread count restored
