@@ -301,9 +301,10 @@ def _minor_case(rng, K, modes):
 def test_minors_vs_oracle(oracle):
     """perm_minors (one joint leave-one-column-out walk) against the oracle's
     generalized permanent of every column-deleted matrix: K = 2..24 over 60
-    modes (one and two target groups) and K up to 36 with heavy bunching."""
+    modes (one and two target groups) and K up to 44 with heavy bunching (one
+    group up to 36 columns, two groups at 37 and 44)."""
     rng = np.random.default_rng(303)
-    cases = [(K, 60) for K in (2, 3, 4, 7, 12, 16, 20, 24)] + [(K, 5) for K in (28, 33, 36)]
+    cases = [(K, 60) for K in (2, 3, 4, 7, 12, 16, 20, 24)] + [(K, 5) for K in (28, 33, 36, 37)] + [(44, 4)]
     for K, modes in cases:
         A, M = _minor_case(rng, K, modes)
         say(f"case minors K={K} M={M.tolist()}")
