@@ -299,6 +299,8 @@ def main():
     ap.add_argument("--no-t0-fit", action="store_true", help="skip the sampling-time model fit")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run one plain device-to-device copy of this size (HBM counter calibration)")
+    ap.add_argument("--minors-probe", type=int, default=0,
+                    help="only run perm_minors on a K-column Haar minor (K - 1 rows, M = 1) ten times (kernel profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the permanent and sampler paths run on a single device "
@@ -322,6 +324,15 @@ def main():
         print(json.dumps({"copy_probe_bytes_read": n, "copy_probe_bytes_written": n}), flush=True)
         return
     B.init()
+    if args.minors_probe:
+        K = args.minors_probe
+        A = torch.from_numpy(np.ascontiguousarray(I.haar_unitary(0)[:K - 1, :K])).to("cuda")
+        ms = []
+        for _ in range(10):  # the last calls run at the sustained clock
+            B.perm_minors(A, np.ones(K - 1, dtype=np.int32))
+            ms.append(round(B.batch_last_kernel_ms(), 4))
+        print(json.dumps({"minors_probe_columns": K, "n_addends_per_group": 2 ** (K - 2), "kernel_ms": ms}), flush=True)
+        return
     inputs = {}
     for c in CASES:
         A, M = I.c2(c)
