@@ -3,6 +3,8 @@
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
                     [--serve-jobs J] [--no-serving] [--no-batch] [--no-autotune]
                     [--large-samples S] [--no-t0-fit]
+    python bench.py --minors-probe K      (profiling: perm_minors on K columns only)
+    python bench.py --copy-probe-mib MiB  (profiling: one plain device copy, HBM counter calibration)
 
 Headline workload (synthetic, seeded): the three single n = 30 generalized
 permanents of a 60 x 60 Haar unitary (seed 0):
