@@ -291,15 +291,21 @@ BBFG_FN void walk_unit(const WalkArgs& A, const PermDesc& d, uint32_t u_local, u
 // = ws * (prod_{j < T} c_j) * (prod_{i < t} c_{T+i}) * (prod_{t < i < G} c_{T+i}):
 // one product of the leading sums, prefix products over the targets, and a
 // running suffix product (about K + 2G complex products for G permanents).
+// The weight ws enters the first prefix product, so each target's update is
+// one complex multiply-accumulate of its prefix and suffix products: four
+// fused multiply-adds instead of a complex product and a weighted add.
 template <int K, int G, typename Real>
 BBFG_FN void minors_accumulate(const Real* re, const Real* im, double ws, double* accr, double* acci)
 {
     constexpr int T = K - G;
     Real pr[G], pim[G];
     if constexpr (T > 0) {
-        cprod<T, Real>(re, im, pr[0], pim[0]);
+        Real cr, ci;
+        cprod<T, Real>(re, im, cr, ci);
+        pr[0] = (Real)(ws * (double)cr);
+        pim[0] = (Real)(ws * (double)ci);
     } else {
-        pr[0] = Real(1);
+        pr[0] = (Real)ws;
         pim[0] = Real(0);
     }
 #pragma unroll
@@ -307,15 +313,14 @@ BBFG_FN void minors_accumulate(const Real* re, const Real* im, double ws, double
     Real sr = Real(1), si = Real(0);
 #pragma unroll
     for (int t = G - 1; t >= 0; --t) {
-        Real xr, xi;
         if (t == G - 1) {
-            xr = pr[t];
-            xi = pim[t];
+            accr[t] = accr[t] + (double)pr[t];
+            acci[t] = acci[t] + (double)pim[t];
         } else {
-            cmul<Real>(pr[t], pim[t], sr, si, xr, xi);
+            const double ar = (double)pr[t], ai = (double)pim[t], br = (double)sr, bi = (double)si;
+            accr[t] = __builtin_fma(-ai, bi, __builtin_fma(ar, br, accr[t]));
+            acci[t] = __builtin_fma(ai, br, __builtin_fma(ar, bi, acci[t]));
         }
-        accr[t] = __builtin_fma(ws, (double)xr, accr[t]);
-        acci[t] = __builtin_fma(ws, (double)xi, acci[t]);
         if (t > 0) {
             if (t == G - 1) {
                 sr = re[T + t];
