@@ -70,15 +70,19 @@ struct PermDesc {
 
 // Leave-one-column-out walks over K columns cover the targets in groups of
 // minor_group(K): one group keeps K column sums, G prefix products and G
-// accumulators per lane (4K + 8G FP64 registers).  Up to 24 columns the groups
-// stay small enough for two wavefronts per SIMD (<= 256 VGPRs); above, where the
-// sums are long and work dominates, one wavefront per SIMD with the fewest
-// groups that fit 512 registers without spilling to scratch does fewer products
-// per addend (one group up to 36 columns: K + 2G - 4 complex products instead of
-// about 1.6 times that), which measured 1.2-1.25 times faster at 28-36 columns.
+// accumulators per lane (4K + 8G FP64 registers).  Up to 30 columns the groups
+// stay small enough for two wavefronts per SIMD (<= 256 VGPRs): up to 24
+// columns groups of at most 27 - K/2 targets, at 25-30 columns two groups (the
+// kernel for up to 30 columns is built for two wavefronts per SIMD).  Above,
+// where the sums are long and work dominates, one wavefront per SIMD with the
+// fewest groups that fit 512 registers without spilling to scratch does fewer
+// products per addend (one group up to 36 columns: K + 2G - 4 complex products
+// instead of about 1.6 times that), which measured 1.2-1.25 times faster at
+// 31-36 columns than three groups at two wavefronts; at 25-30 columns two
+// groups at two wavefronts measured 4-9 % faster than one group at one.
 constexpr int minor_group(int K)
 {
-    int gmax = (K <= 24 ? 27 : 54) - K / 2;
+    int gmax = K <= 24 ? 27 - K / 2 : (K <= 30 ? (K + 1) / 2 : 54 - K / 2);
     if (gmax < 1) gmax = 1;
     if (gmax > K) gmax = K;
     const int groups = (K + gmax - 1) / gmax;

@@ -12,6 +12,8 @@ namespace bbfg {
 const void* walk_single_fn(int n, int f32);
 const void* walk_batch_fn(int bucket, int f32);
 int batch_bucket_max(int nmax, int f32);
+// smallest leave-one-column-out kernel for nmax columns (adds a 30-column one)
+int minors_bucket_max(int nmax);
 
 hipError_t launch_walk_single(int n, int f32, uint32_t grid, hipStream_t s, const WalkArgs& A, uint32_t item);
 hipError_t launch_walk_batch(int bucket, int f32, uint32_t grid, hipStream_t s, const WalkArgs& A);
@@ -26,6 +28,7 @@ hipError_t launch_walk_cols(int bucket, uint32_t grid, hipStream_t s, const Walk
 const void* walk_minors_fn(int bucket);
 const void* walk_minors_fn_b16();
 const void* walk_minors_fn_b24();
+const void* walk_minors_fn_b30();
 const void* walk_minors_fn_b32();
 const void* walk_minors_fn_b48();
 hipError_t launch_walk_minors(int bucket, uint32_t grid, hipStream_t s, const WalkArgs& A);

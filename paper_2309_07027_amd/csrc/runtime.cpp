@@ -509,7 +509,7 @@ int run_perms(Context& c, Workspace& w, std::vector<PermItem>& items, int f32, b
     int bucket = 0;
     uint64_t grid = total_units;
     if (!single) {
-        bucket = batch_bucket_max(nmax, f32);
+        bucket = minors ? minors_bucket_max(nmax) : batch_bucket_max(nmax, f32);
         if (bucket < 0) return set_error(BBFG_ERANGE, "no batch kernel for n=%d", nmax);
         int waves = 1;
         BBFG_TRY(batch_waves(c, bucket, minors ? kKindMinors : (powcols ? kKindCols : f32), &waves));

@@ -196,6 +196,12 @@ int batch_bucket_max(int nmax, int f32)
     return -1;
 }
 
+int minors_bucket_max(int nmax)
+{
+    if (nmax > 24 && nmax <= 30) return 30;
+    return batch_bucket_max(nmax, 0);
+}
+
 const void* walk_batch_fn(int bucket, int f32)
 {
     if (f32) {
@@ -238,6 +244,7 @@ const void* walk_minors_fn(int bucket)
     switch (bucket) {
     case 16: return walk_minors_fn_b16();
     case 24: return walk_minors_fn_b24();
+    case 30: return walk_minors_fn_b30();
     case 32: return walk_minors_fn_b32();
     case 48: return walk_minors_fn_b48();
     default: return nullptr;

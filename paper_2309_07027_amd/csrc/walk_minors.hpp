@@ -39,8 +39,11 @@ __device__ __forceinline__ void dispatch_minors(const WalkArgs& A, const PermDes
     }
 }
 
+// Kernels for up to 30 columns are built for two wavefronts per SIMD (their
+// paths fit 256 VGPRs; the few spilled values live outside the walk loops),
+// wider ones for one.
 template <int KMAX>
-__global__ __launch_bounds__(kWave) void walk_minors_batch_kernel(WalkArgs A)
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(KMAX <= 30 ? 2 : 1))) void walk_minors_batch_kernel(WalkArgs A)
 {
     __shared__ uint32_t next_unit;
     for (;;) {
