@@ -347,7 +347,10 @@ int bbfg_gray_table(const int32_t *radices, int32_t n_digits, int32_t max_len,
 int bbfg_fp64_fma_peak(double *tflops, double *ms);
 
 /* Resident wavefronts per compute unit of the walk kernel for n_cols columns
- * and the number of compute units (device query).  Errors: BBFG_EDEVICE. */
+ * and the number of compute units (device query).  precision BBFG_MINORS: the
+ * leave-one-column-out kernel for n_cols >= 2 columns (perm_minors splits its
+ * walk into whole rounds of those wavefronts).  Errors: BBFG_ERANGE,
+ * BBFG_EDEVICE. */
 int bbfg_walk_occupancy(int32_t n_cols, int32_t precision, int32_t *waves_per_cu, int32_t *n_cu);
 
 #ifdef __cplusplus

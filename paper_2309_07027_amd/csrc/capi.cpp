@@ -251,7 +251,7 @@ try {
     proto.mult = row_mult;
     // a lone call splits its sums to fill the device (the sampler's minors use
     // the batch split, which depends on the item's shape only)
-    BBFG_TRY(get_plan(*c, row_mult, n_rows, n_cols - 1, 0, PLAN_SINGLE, &proto.plan));
+    BBFG_TRY(get_plan(*c, row_mult, n_rows, n_cols - 1, kKindMinors, PLAN_SINGLE, &proto.plan));
     std::vector<int32_t> cols((size_t)n_cols);
     for (int32_t j = 0; j < n_cols; ++j) cols[(size_t)j] = j;
     std::deque<std::vector<int32_t>> keep;
@@ -438,12 +438,19 @@ BBFG_API_CATCH
 int bbfg_walk_occupancy(int32_t n_cols, int32_t precision, int32_t* waves_per_cu, int32_t* n_cu)
 try {
     const int f32 = precision == BBFG_FP32 ? 1 : 0;
-    if (n_cols < 1 || n_cols > (f32 ? kMaxNF32 : kMaxN)) return set_error(BBFG_ERANGE, "n_cols out of range");
+    const bool minors = precision == BBFG_MINORS;
+    if (n_cols < (minors ? 2 : 1) || n_cols > (f32 ? kMaxNF32 : kMaxN)) return set_error(BBFG_ERANGE, "n_cols out of range");
     Context* c = nullptr;
     BBFG_TRY(get_context(&c));
     std::lock_guard<std::recursive_mutex> lk(c->mu);
     uint64_t S = 0;
-    BBFG_TRY(walk_slots(*c, n_cols, f32, &S));
+    if (minors) {
+        int waves = 1;
+        BBFG_TRY(batch_waves(*c, minors_bucket_max(n_cols), kKindMinors, &waves));
+        S = (uint64_t)waves * (uint64_t)c->n_cu;
+    } else {
+        BBFG_TRY(walk_slots(*c, n_cols, f32, &S));
+    }
     if (waves_per_cu) *waves_per_cu = (int32_t)(S / (uint64_t)c->n_cu);
     if (n_cu) *n_cu = c->n_cu;
     return BBFG_OK;

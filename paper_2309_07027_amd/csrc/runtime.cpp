@@ -237,7 +237,17 @@ int get_plan(Context& c, const int32_t* mult, int n_rows, int n_cols, int f32, i
         return BBFG_OK;
     }
     uint64_t slots = 1;
-    if (n_cols >= 1) BBFG_TRY(walk_slots(c, n_cols, f32 == 1 ? 1 : 0, &slots));
+    if (f32 == kKindMinors && mode == PLAN_SINGLE) {
+        // a lone leave-one-column-out walk fills the minors kernel's own
+        // resident wavefronts (K = n_cols + 1 columns)
+        const int bucket = minors_bucket_max(n_cols + 1);
+        if (bucket < 0) return set_error(BBFG_ERANGE, "no minors kernel for %d columns", n_cols + 1);
+        int waves = 1;
+        BBFG_TRY(batch_waves(c, bucket, kKindMinors, &waves));
+        slots = (uint64_t)waves * (uint64_t)c.n_cu;
+    } else if (n_cols >= 1) {
+        BBFG_TRY(walk_slots(c, n_cols, f32 == 1 ? 1 : 0, &slots));
+    }
     if (c.tables.entries > c.table_entry_cap || c.plans.size() >= c.plan_cap) BBFG_TRY(flush_plans(c));
     auto p = std::make_shared<HostPlan>();
     std::string err;

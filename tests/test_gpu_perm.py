@@ -323,7 +323,7 @@ def test_minors_match_emulation_bitwise():
         A, M = _minor_case(rng, K, modes)
         say(f"case minors emulation K={K} M={M.tolist()}")
         g = B.perm_minors(A, M)
-        waves, ncu = B.walk_occupancy(K - 1)
+        waves, ncu = B.walk_occupancy(K, B.BBFG_MINORS)  # the split fills the minors kernel
         e = emu.run_minors(A, M, 0, slots=waves * ncu)
         assert np.array_equal(g, e), K
 
