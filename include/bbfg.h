@@ -63,8 +63,9 @@ typedef enum {
 } bbfg_status;
 
 /* BBFG_MINORS names the batched leave-one-column-out walks (FP64) in the
- * autotuner calls only. */
-typedef enum { BBFG_FP64 = 0, BBFG_FP32 = 1, BBFG_MINORS = 2 } bbfg_precision;
+ * autotuner calls and bbfg_walk_occupancy; BBFG_COLS names the column-power
+ * kernel in bbfg_walk_occupancy only. */
+typedef enum { BBFG_FP64 = 0, BBFG_FP32 = 1, BBFG_MINORS = 2, BBFG_COLS = 3 } bbfg_precision;
 
 typedef struct {
     double re, im;
@@ -349,8 +350,10 @@ int bbfg_fp64_fma_peak(double *tflops, double *ms);
 /* Resident wavefronts per compute unit of the walk kernel for n_cols columns
  * and the number of compute units (device query).  precision BBFG_MINORS: the
  * leave-one-column-out kernel for n_cols >= 2 columns (perm_minors splits its
- * walk into whole rounds of those wavefronts).  Errors: BBFG_ERANGE,
- * BBFG_EDEVICE. */
+ * walk into whole rounds of those wavefronts); precision BBFG_COLS (accepted
+ * only here): the column-power kernel for n_cols distinct columns, which runs
+ * perm_bbfg_cols when every column multiplicity is the same e >= 2.  Errors:
+ * BBFG_ERANGE, BBFG_EDEVICE. */
 int bbfg_walk_occupancy(int32_t n_cols, int32_t precision, int32_t *waves_per_cu, int32_t *n_cu);
 
 #ifdef __cplusplus

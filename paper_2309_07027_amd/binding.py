@@ -24,6 +24,7 @@ BBFG_ENOTFOUND = -6
 BBFG_FP64 = 0
 BBFG_FP32 = 1
 BBFG_MINORS = 2
+BBFG_COLS = 3
 MAX_N = 48
 MAX_N_FP32 = 24
 

@@ -329,7 +329,8 @@ try {
             for (int32_t t = 0; t < col_mult[j]; ++t) cmap.push_back(j);
     }
     it.col_map = cmap.data();
-    BBFG_TRY(get_plan(*c, row_mult, n_rows, (int)n, 0, PLAN_SINGLE, &it.plan));
+    if (single) BBFG_TRY(get_plan(*c, row_mult, n_rows, (int)n, 0, PLAN_SINGLE, &it.plan));
+    else BBFG_TRY(get_plan(*c, row_mult, n_rows, (int)n, kKindCols, PLAN_SINGLE, &it.plan, it.arena_cols));
     double res[2], diag[2];
     RunResult rr;
     BBFG_TRY(run_perms(*c, items, 0, single, res, diag, &rr));
@@ -439,14 +440,17 @@ int bbfg_walk_occupancy(int32_t n_cols, int32_t precision, int32_t* waves_per_cu
 try {
     const int f32 = precision == BBFG_FP32 ? 1 : 0;
     const bool minors = precision == BBFG_MINORS;
+    const bool cols = precision == BBFG_COLS;
     if (n_cols < (minors ? 2 : 1) || n_cols > (f32 ? kMaxNF32 : kMaxN)) return set_error(BBFG_ERANGE, "n_cols out of range");
     Context* c = nullptr;
     BBFG_TRY(get_context(&c));
     std::lock_guard<std::recursive_mutex> lk(c->mu);
     uint64_t S = 0;
-    if (minors) {
+    if (minors || cols) {
         int waves = 1;
-        BBFG_TRY(batch_waves(*c, minors_bucket_max(n_cols), kKindMinors, &waves));
+        const int bucket = minors ? minors_bucket_max(n_cols) : batch_bucket_max(n_cols, 0);
+        if (bucket < 0) return set_error(BBFG_ERANGE, "no kernel for %d columns", n_cols);
+        BBFG_TRY(batch_waves(*c, bucket, minors ? kKindMinors : kKindCols, &waves));
         S = (uint64_t)waves * (uint64_t)c->n_cu;
     } else {
         BBFG_TRY(walk_slots(*c, n_cols, f32, &S));

@@ -221,7 +221,7 @@ int load_autotune_file(Context& c, const char* path)
 }
 
 int get_plan(Context& c, const int32_t* mult, int n_rows, int n_cols, int f32, int mode,
-             std::shared_ptr<const HostPlan>* out)
+             std::shared_ptr<const HostPlan>* out, int kernel_cols)
 {
     PlanParams pp = c.params;
     if (mode == PLAN_BATCH) pp.l_batch = batch_unit_length(c, n_cols, f32);
@@ -230,6 +230,7 @@ int get_plan(Context& c, const int32_t* mult, int n_rows, int n_cols, int f32, i
     key.append(reinterpret_cast<const char*>(&n_cols), sizeof n_cols);
     key.push_back((char)f32);
     key.append(reinterpret_cast<const char*>(&pp.l_batch), sizeof pp.l_batch);
+    key.append(reinterpret_cast<const char*>(&kernel_cols), sizeof kernel_cols);
     key.append(reinterpret_cast<const char*>(mult), sizeof(int32_t) * (size_t)n_rows);
     auto it = c.plans.find(key);
     if (it != c.plans.end()) {
@@ -244,6 +245,14 @@ int get_plan(Context& c, const int32_t* mult, int n_rows, int n_cols, int f32, i
         if (bucket < 0) return set_error(BBFG_ERANGE, "no minors kernel for %d columns", n_cols + 1);
         int waves = 1;
         BBFG_TRY(batch_waves(c, bucket, kKindMinors, &waves));
+        slots = (uint64_t)waves * (uint64_t)c.n_cu;
+    } else if (f32 == kKindCols && mode == PLAN_SINGLE) {
+        // (prod_j c_j)^e over kernel_cols distinct columns: the column-power
+        // kernel's resident wavefronts
+        const int bucket = batch_bucket_max(kernel_cols, 0);
+        if (bucket < 0) return set_error(BBFG_ERANGE, "no column-power kernel for %d columns", kernel_cols);
+        int waves = 1;
+        BBFG_TRY(batch_waves(c, bucket, kKindCols, &waves));
         slots = (uint64_t)waves * (uint64_t)c.n_cu;
     } else if (n_cols >= 1) {
         BBFG_TRY(walk_slots(c, n_cols, f32 == 1 ? 1 : 0, &slots));

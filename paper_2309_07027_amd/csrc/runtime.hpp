@@ -175,8 +175,12 @@ constexpr int kKindCols = 3;  // uniform column multiplicities
 int batch_waves(Context& c, int bucket, int kind, int* waves);
 // kind = 0 (FP64), 1 (FP32) or BBFG_MINORS: selects the tuned unit length of
 // PLAN_BATCH plans (plans of different kinds are cached separately).
+// PLAN_SINGLE plans fill the resident wavefronts of the kernel that runs them:
+// the plain walk for n_cols columns, the minors kernel for n_cols + 1 columns
+// (kind kKindMinors), or the column-power kernel for kernel_cols distinct
+// columns (kind kKindCols).
 int get_plan(Context& c, const int32_t* mult, int n_rows, int n_cols, int kind, int mode,
-             std::shared_ptr<const HostPlan>* out);
+             std::shared_ptr<const HostPlan>* out, int kernel_cols = 0);
 // Pool space for a device table of `bytes` bytes (resident until a flush).
 int table_reserve(Context& c, size_t bytes, TabEntry** out);
 // Caches are bounded (Context::plan_cap, Context::table_entry_cap): past these

@@ -408,7 +408,10 @@ def test_column_multiplicities_vs_oracle_and_expansion(oracle):
             ref = oracle.perm_generalized(Ax, M)
             assert rel(v, ref) <= TOL, (n, N.tolist())
         if n <= 24:  # the sanitised CPU emulation is slow beyond
-            waves, ncu = B.walk_occupancy(int(N.sum()))  # the split is planned for n = sum(N) columns
+            if modes_in > 0:  # mixed multiplicities: the expanded walk of n = sum(N) columns
+                waves, ncu = B.walk_occupancy(int(N.sum()))
+            else:  # equal multiplicities: the column-power kernel over the distinct columns
+                waves, ncu = B.walk_occupancy(len(N), B.BBFG_COLS)
             e, *_ = emu.run_cols(A, M, N, waves * ncu)
             assert v == e, (n, v, e)
 
