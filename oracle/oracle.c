@@ -401,15 +401,30 @@ int oracle_perm_glynn_gray(int n, const double *A, int64_t first, int64_t count,
 /* abs_sum (nullable) receives 2^{1-n} sum |addend|.                          */
 /* ------------------------------------------------------------------------- */
 
-static uint64_t binom_u64(int m, int k)
+/* Binomial coefficients from Pascal's triangle, C(m, k) = C(m-1, k-1) +
+ * C(m-1, k) with C(m, 0) = C(m, m) = 1, for 0 <= k <= m <= 64.  Every entry is
+ * an exact integer (the largest, C(64, 32) ~ 1.8e18, is below 2^63).  The
+ * triangle is filled once when the library is loaded. */
+#define PASCAL_ROWS 65
+static uint64_t pascal_tri[PASCAL_ROWS][PASCAL_ROWS];
+
+__attribute__((constructor)) static void pascal_fill(void)
 {
-    if (k < 0 || k > m) return 0;
-    unsigned __int128 c = 1;
-    for (int i = 1; i <= k; ++i) c = c * (unsigned)(m - k + i) / (unsigned)i;
-    return (uint64_t)c;
+    for (int row = 0; row < PASCAL_ROWS; ++row) {
+        pascal_tri[row][0] = 1;
+        for (int col = 1; col < row; ++col)
+            pascal_tri[row][col] = pascal_tri[row - 1][col - 1] + pascal_tri[row - 1][col];
+        pascal_tri[row][row] = 1;
+    }
 }
 
-uint64_t oracle_binom(int m, int k) { return binom_u64(m, k); }
+static uint64_t choose(int m, int k)
+{
+    if (m < 0 || m >= PASCAL_ROWS || k < 0 || k > m) return 0;
+    return pascal_tri[m][k];
+}
+
+uint64_t oracle_binom(int m, int k) { return choose(m, k); }
 
 static int choose_pivot(int r, const int *M)
 {
@@ -456,7 +471,7 @@ int oracle_perm_generalized(int r, int n, const double *A, const int *M, int piv
             /* weight prod_k (-1)^{Delta_k} C(M'_k, Delta_k): an exact integer <= 2^{n-1} */
             uint64_t w = 1;
             int parity = 0;
-            for (int k = 0; k < r; ++k) { w *= binom_u64(Mp[k], D[k]); parity += D[k]; }
+            for (int k = 0; k < r; ++k) { w *= choose(Mp[k], D[k]); parity += D[k]; }
             cdd p = cdd_one();
             for (int j = 0; j < n; ++j) {
                 cdd cs = cdd_from(A + 2 * (pivot * n + j));
@@ -507,7 +522,7 @@ int oracle_perm_generalized_full(int r, int n, const double *A, const int *M, do
     for (uint64_t idx = 0; idx < total; ++idx) {
         uint64_t w = 1;
         int parity = 0;
-        for (int k = 0; k < r; ++k) { w *= binom_u64(M[k], D[k]); parity += D[k]; }
+        for (int k = 0; k < r; ++k) { w *= choose(M[k], D[k]); parity += D[k]; }
         cdd p = cdd_one();
         for (int j = 0; j < n; ++j) {
             cdd cs = cdd_zero();
@@ -525,6 +540,75 @@ int oracle_perm_generalized_full(int r, int n, const double *A, const int *M, do
         }
     }
     cdd_store(cdd_scale_d(acc, pow2i(-n)), out);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Eq. (ryser) with row multiplicities (the generalized Ryser formula that   */
+/* Sec. 2.2 cites).  perm(A) = perm(A^T), so the subsets may run over rows   */
+/* instead of columns.  Row k of the r x n matrix A stands for M_k identical */
+/* rows; a subset that takes s_k of those copies can do so in C(M_k, s_k)    */
+/* ways, all giving the same addend, hence                                   */
+/*                                                                           */
+/*   perm(A, M) = (-1)^n sum_{s_k in [0, M_k]} (-1)^{s_1 + ... + s_r}         */
+/*                 prod_k C(M_k, s_k) prod_j ( sum_k s_k a_kj ).              */
+/*                                                                           */
+/* The inner sums hold a varying number of matrix elements (the reason the  */
+/* paper gives, Sec. 3.2, for Ryser's weaker accuracy).  s runs over the box */
+/* in lexicographic order with every inner sum recomputed from scratch.      */
+/* abs_sum (nullable) receives sum |addend|.                                  */
+/* ------------------------------------------------------------------------- */
+
+int oracle_perm_ryser_generalized(int r, int n, const double *A, const int *M, double *out, double *abs_sum)
+{
+    if (r < 0 || n < 0 || n > 64 || r > 64) return -1;
+    int sum = 0;
+    for (int k = 0; k < r; ++k) { if (M[k] < 0) return -1; sum += M[k]; }
+    if (sum != n) return -1;
+    if (n == 0) { cdd_store(cdd_one(), out); if (abs_sum) *abs_sum = 1.0; return 0; }
+    uint64_t total = 1;
+    for (int k = 0; k < r; ++k) total *= (uint64_t)(M[k] + 1);
+    const int nb = total < NBLOCKS ? (int)total : NBLOCKS;
+    cdd *part = (cdd *)calloc((size_t)nb, sizeof(cdd));
+    double *apart = (double *)calloc((size_t)nb, sizeof(double));
+    if (!part || !apart) { free(part); free(apart); return -2; }
+
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int b = 0; b < nb; ++b) {
+        uint64_t lo = block_lo(total, b, nb), hi = block_lo(total, b + 1, nb);
+        int s_cnt[64];
+        uint64_t x = lo;
+        for (int k = 0; k < r; ++k) { s_cnt[k] = (int)(x % (uint64_t)(M[k] + 1)); x /= (uint64_t)(M[k] + 1); }
+        cdd acc = cdd_zero();
+        double aacc = 0.0;
+        for (uint64_t idx = lo; idx < hi; ++idx) {
+            uint64_t ways = 1;
+            int picked = 0;
+            for (int k = 0; k < r; ++k) { ways *= choose(M[k], s_cnt[k]); picked += s_cnt[k]; }
+            cdd p = cdd_one();
+            for (int j = 0; j < n; ++j) {
+                cdd inner = cdd_zero();
+                for (int k = 0; k < r; ++k)
+                    if (s_cnt[k]) inner = cdd_axpy_d(inner, (double)s_cnt[k], A + 2 * (k * n + j));
+                p = cdd_mul(p, inner);
+            }
+            p = cdd_scale_d(p, ((picked + n) & 1) ? -(double)ways : (double)ways);
+            acc = cdd_add(acc, p);
+            aacc += cdd_abs_d(p);
+            for (int k = 0; k < r; ++k) {
+                if (s_cnt[k] < M[k]) { s_cnt[k]++; break; }
+                s_cnt[k] = 0;
+            }
+        }
+        part[b] = acc;
+        apart[b] = aacc;
+    }
+    cdd acc = cdd_zero();
+    double aacc = 0.0;
+    for (int b = 0; b < nb; ++b) { acc = cdd_add(acc, part[b]); aacc += apart[b]; }
+    free(part); free(apart);
+    cdd_store(acc, out);
+    if (abs_sum) *abs_sum = aacc;
     return 0;
 }
 
@@ -698,34 +782,23 @@ static int draw_index(int rows, const double *w, double u)
     return rows - 1;
 }
 
-/* out_occ: n_samples x m occupations (int32).  loss in [0,1): 0 = ideal. */
-int oracle_cc_sample(int m, const double *U, const int *input_occ, int n_samples,
-                     double loss, uint64_t seed, int *out_occ)
+/* Samples of the photons entering the input modes of `src` (rows x ld,
+ * row-major; column i is input mode i, i < m): A = the columns picked by the
+ * input occupation (rows x n), every one of the `rows` rows a candidate
+ * output mode, the occupation of the first m rows reported.  Random numbers
+ * as described above. */
+static int cc_sample_rows(int rows, int m, const double *src, int ld, const int *input_occ, int n,
+                          int n_samples, uint64_t seed, int *out_occ)
 {
-    if (m < 1 || m > 128 || n_samples < 0 || !(loss >= 0.0 && loss < 1.0)) return -1;
-    int n = 0;
-    for (int i = 0; i < m; ++i) { if (input_occ[i] < 0) return -1; n += input_occ[i]; }
-    if (n > 24) return -1;
-    int rows = loss > 0.0 ? 2 * m : m;
-    double *W = NULL;
-    const double *src = U;
-    int ld = m;
-    if (loss > 0.0) {
-        W = (double *)malloc(sizeof(double) * 2 * (size_t)rows * (size_t)rows);
-        if (!W) return -2;
-        build_dilation(m, U, 1.0 - loss, W);
-        src = W; ld = rows;
-    }
-    /* A: rows x n, column b is input mode cols[b] */
     double *A = (double *)malloc(sizeof(double) * 2 * (size_t)rows * (size_t)(n > 0 ? n : 1));
     double *w = (double *)malloc(sizeof(double) * (size_t)rows);
-    if (!A || !w) { free(W); free(A); free(w); return -2; }
+    if (!A || !w) { free(A); free(w); return -2; }
     int cols[64], c = 0;
     for (int i = 0; i < m; ++i) for (int t = 0; t < input_occ[i]; ++t) cols[c++] = i;
     for (int r = 0; r < rows; ++r)
         for (int b = 0; b < n; ++b) {
-            A[2 * (r * n + b)] = src[2 * (r * ld + cols[b])];
-            A[2 * (r * n + b) + 1] = src[2 * (r * ld + cols[b]) + 1];
+            A[2 * (r * n + b)] = src[2 * ((size_t)r * ld + cols[b])];
+            A[2 * (r * n + b) + 1] = src[2 * ((size_t)r * ld + cols[b]) + 1];
         }
     int rc = 0;
     for (int s = 0; s < n_samples && rc == 0; ++s) {
@@ -748,6 +821,120 @@ int oracle_cc_sample(int m, const double *U, const int *input_occ, int n_samples
         for (int i = 0; i < m; ++i) o[i] = 0;
         for (int k = 0; k < n; ++k) if (prefix[k] < m) o[prefix[k]]++;
     }
-    free(W); free(A); free(w);
+    free(A); free(w);
+    return rc;
+}
+
+static int count_photons(int m, const int *input_occ)
+{
+    int n = 0;
+    for (int i = 0; i < m; ++i) { if (input_occ[i] < 0) return -1; n += input_occ[i]; }
+    return n;
+}
+
+/* out_occ: n_samples x m occupations (int32).  loss in [0,1): 0 = ideal. */
+int oracle_cc_sample(int m, const double *U, const int *input_occ, int n_samples,
+                     double loss, uint64_t seed, int *out_occ)
+{
+    if (m < 1 || m > 128 || n_samples < 0 || !(loss >= 0.0 && loss < 1.0)) return -1;
+    int n = count_photons(m, input_occ);
+    if (n < 0 || n > 24) return -1;
+    if (loss == 0.0) return cc_sample_rows(m, m, U, m, input_occ, n, n_samples, seed, out_occ);
+    double *W = (double *)malloc(sizeof(double) * 2 * (size_t)(2 * m) * (size_t)(2 * m));
+    if (!W) return -2;
+    build_dilation(m, U, 1.0 - loss, W);
+    int rc = cc_sample_rows(2 * m, m, W, 2 * m, input_occ, n, n_samples, seed, out_occ);
+    free(W);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Non-uniform loss (Sec. 4): a lossy interferometer is described by a       */
+/* matrix T that is no longer unitary, a contraction (T^H T <= I).  With     */
+/* the photons entering the first m of 2m modes, the sampled law depends     */
+/* only on the first m columns of a 2m x 2m unitary dilation of T, i.e. on   */
+/* an isometry V = [T; B] with B^H B = I - T^H T; every such B gives the     */
+/* same law on the first m output modes (two choices differ by a unitary    */
+/* acting on the unmeasured modes only).  B is taken here as the upper       */
+/* triangular Cholesky factor R of I - T^H T (R^H R = I - T^H T, real        */
+/* non-negative diagonal; a pivot that rounding leaves in [-1e-10, 0] is     */
+/* set to zero together with the rest of its row).  Returns -3 when a pivot  */
+/* is below -1e-10, i.e. T is not a contraction.                             */
+/* ------------------------------------------------------------------------- */
+
+#define CONTRACTION_TOL 1e-10
+
+static int contraction_isometry(int m, const double *T, double *V)
+{
+    /* G = I - T^H T, accumulated in double-double */
+    double *G = (double *)malloc(sizeof(double) * 2 * (size_t)m * (size_t)m);
+    if (!G) return -2;
+    for (int j = 0; j < m; ++j)
+        for (int k = 0; k < m; ++k) {
+            cdd acc = cdd_zero();
+            for (int i = 0; i < m; ++i) {
+                const double *a = T + 2 * (i * m + j), *b = T + 2 * (i * m + k);
+                cdd ca; ca.re = dd_make(a[0]); ca.im = dd_make(-a[1]);
+                acc = cdd_add(acc, cdd_mul(ca, cdd_from(b)));
+            }
+            double re = (j == k ? 1.0 : 0.0) - dd_to_d(acc.re);
+            double im = -dd_to_d(acc.im);
+            G[2 * (j * m + k)] = re;
+            G[2 * (j * m + k) + 1] = im;
+        }
+    double *R = V + 2 * (size_t)m * (size_t)m; /* rows m .. 2m-1 of V */
+    memset(R, 0, sizeof(double) * 2 * (size_t)m * (size_t)m);
+    int rc = 0;
+    /* Cholesky-Crout, one row of R at a time:
+     *   R_jj = sqrt(G_jj - sum_{i<j} |R_ij|^2),
+     *   R_jk = (G_jk - sum_{i<j} conj(R_ij) R_ik) / R_jj   (k > j). */
+    for (int j = 0; j < m && rc == 0; ++j) {
+        double d = G[2 * (j * m + j)];
+        for (int i = 0; i < j; ++i) {
+            const double *x = R + 2 * (i * m + j);
+            d -= x[0] * x[0] + x[1] * x[1];
+        }
+        if (d < -CONTRACTION_TOL) { rc = -3; break; }
+        if (d <= 0.0) continue;
+        double rjj = sqrt(d);
+        R[2 * (j * m + j)] = rjj;
+        for (int k = j + 1; k < m; ++k) {
+            double re = G[2 * (j * m + k)], im = G[2 * (j * m + k) + 1];
+            for (int i = 0; i < j; ++i) {
+                const double *x = R + 2 * (i * m + j), *y = R + 2 * (i * m + k);
+                /* conj(x) * y */
+                re -= x[0] * y[0] + x[1] * y[1];
+                im -= x[0] * y[1] - x[1] * y[0];
+            }
+            R[2 * (j * m + k)] = re / rjj;
+            R[2 * (j * m + k) + 1] = im / rjj;
+        }
+    }
+    free(G);
+    if (rc == 0) memcpy(V, T, sizeof(double) * 2 * (size_t)m * (size_t)m);
+    return rc;
+}
+
+/* V: 2m x m isometry [T; R] (row-major). */
+int oracle_contraction_isometry(int m, const double *T, double *V)
+{
+    if (m < 1 || m > 128) return -1;
+    return contraction_isometry(m, T, V);
+}
+
+/* Clifford & Clifford samples through the lossy interferometer T (m x m
+ * contraction): the 2m rows of V = [T; R] are the candidate output modes, the
+ * first m are reported.  Random numbers as in oracle_cc_sample. */
+int oracle_cc_sample_lossy(int m, const double *T, const int *input_occ, int n_samples, uint64_t seed,
+                           int *out_occ)
+{
+    if (m < 1 || m > 128 || n_samples < 0) return -1;
+    int n = count_photons(m, input_occ);
+    if (n < 0 || n > 24) return -1;
+    double *V = (double *)malloc(sizeof(double) * 2 * (size_t)(2 * m) * (size_t)m);
+    if (!V) return -2;
+    int rc = contraction_isometry(m, T, V);
+    if (rc == 0) rc = cc_sample_rows(2 * m, m, V, m, input_occ, n, n_samples, seed, out_occ);
+    free(V);
     return rc;
 }

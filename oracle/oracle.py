@@ -68,6 +68,9 @@ def lib():
         L.oracle_cc_weights.argtypes = [ctypes.c_int, ctypes.c_int, _D, _I, ctypes.c_int, _I, _D]
         L.oracle_cc_sample.argtypes = [ctypes.c_int, _D, _I, ctypes.c_int, ctypes.c_double,
                                        ctypes.c_uint64, _I]
+        L.oracle_perm_ryser_generalized.argtypes = [ctypes.c_int, ctypes.c_int, _D, _I, _D, _D]
+        L.oracle_contraction_isometry.argtypes = [ctypes.c_int, _D, _D]
+        L.oracle_cc_sample_lossy.argtypes = [ctypes.c_int, _D, _I, ctypes.c_int, ctypes.c_uint64, _I]
         _lib = L
     return _lib
 
@@ -191,6 +194,22 @@ def perm_generalized_full(A, M) -> complex:
     return _result(out)[0]
 
 
+def perm_ryser_generalized(A, M, with_abs: bool = False, full: bool = False):
+    """Eq. (ryser) over row subsets with row multiplicities, lexicographic, double-double."""
+    A = _cmat(A)
+    r, n = A.shape
+    M = _ivec(M)
+    assert M.shape == (r,)
+    out = np.zeros(4)
+    ab = np.zeros(1)
+    rc = lib().oracle_perm_ryser_generalized(r, n, _dp(A), _ip(M), _dp(out), _dp(ab))
+    if rc:
+        raise ValueError(f"oracle_perm_ryser_generalized rc={rc}")
+    res = _result(out)
+    v = res if full else res[0]
+    return (v, float(ab[0])) if with_abs else v
+
+
 def binom(m: int, k: int) -> int:
     return int(lib().oracle_binom(int(m), int(k)))
 
@@ -249,4 +268,28 @@ def cc_sample(U, input_occ, n_samples: int, loss: float, seed: int) -> np.ndarra
                                 ctypes.c_uint64(seed & (2**64 - 1)), _ip(out))
     if rc:
         raise ValueError(f"oracle_cc_sample rc={rc}")
+    return out
+
+
+def contraction_isometry(T) -> np.ndarray:
+    """V = [T; R] (2m x m) with R the Cholesky factor of I - T^H T (Sec. 4 non-uniform loss)."""
+    T = _cmat(T)
+    m = T.shape[0]
+    V = np.zeros((2 * m, m), dtype=np.complex128)
+    rc = lib().oracle_contraction_isometry(m, _dp(T), _dp(V))
+    if rc:
+        raise ValueError(f"oracle_contraction_isometry rc={rc}")
+    return V
+
+
+def cc_sample_lossy(T, input_occ, n_samples: int, seed: int) -> np.ndarray:
+    """Clifford & Clifford samples through the lossy interferometer matrix T (n_samples x m)."""
+    T = _cmat(T)
+    m = T.shape[0]
+    occ = _ivec(input_occ)
+    out = np.zeros((n_samples, m), dtype=np.int32)
+    rc = lib().oracle_cc_sample_lossy(m, _dp(T), _ip(occ), int(n_samples),
+                                      ctypes.c_uint64(seed & (2**64 - 1)), _ip(out))
+    if rc:
+        raise ValueError(f"oracle_cc_sample_lossy rc={rc}")
     return out

@@ -265,7 +265,7 @@ def test_generalized_zero_multiplicity_and_empty(oracle):
 
 
 def test_binomials(oracle):
-    for m in range(0, 48):
+    for m in range(0, 65):
         for k in range(0, m + 1):
             assert oracle.binom(m, k) == math.comb(m, k)
 
@@ -279,6 +279,124 @@ def test_weight_sum_identity():
         total = sum(math.prod(math.comb(m, d) for m, d in zip(Mp, D))
                     for D in product(*[range(m + 1) for m in Mp]))
         assert total == 2 ** (sum(M) - 1)
+
+
+# ---------------------------------------------------------------------------
+# The magnitude sum 2^{1-n} sum |addend| (the conditioning kappa of Eq. bbfg
+# is abs_sum / |perm|): closed forms where every addend is known, and the
+# identity generalized == row-expanded (the multiset of addends is the same).
+# ---------------------------------------------------------------------------
+
+def _ones_abs_sum(n):
+    # J_n: an addend with k minus signs among rows 2..n is (-1)^k (n - 2k)^n,
+    # and C(n-1, k) sign vectors have k minus signs.
+    return Fraction(sum(math.comb(n - 1, k) * abs(n - 2 * k) ** n for k in range(n)), 2 ** (n - 1))
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 6, 9, 12])
+def test_abs_sum_ones_closed_form(oracle, n):
+    J = np.ones((n, n), dtype=complex)
+    v, ab = oracle.perm_glynn(J, with_abs=True)
+    assert v == math.factorial(n)
+    assert rel(ab, float(_ones_abs_sum(n))) < 1e-14
+    # every partition of the n rows collapses the same multiset of addends
+    for M in ([n], [1] * n, [n - n // 2, n // 2] if n > 1 else [1]):
+        M = [x for x in M if x > 0]
+        g, gab = oracle.perm_generalized(np.ones((len(M), n), dtype=complex), M, with_abs=True)
+        assert g == math.factorial(n)
+        assert rel(gab, float(_ones_abs_sum(n))) < 1e-14
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_abs_sum_diagonal(oracle, seed):
+    # diag(d): every addend equals prod d (the signs cancel), so abs_sum = |prod d|
+    rng = np.random.default_rng(600 + seed)
+    for n in (1, 2, 5, 9):
+        d = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+        expect = float(np.prod(np.abs(d)))
+        _, ab = oracle.perm_glynn(np.diag(d), with_abs=True)
+        assert rel(ab, expect) < 1e-14
+        _, gab = oracle.perm_generalized(np.diag(d), np.ones(n, dtype=np.int32), with_abs=True)
+        assert rel(gab, expect) < 1e-14
+
+
+@pytest.mark.parametrize("M", [[1, 1, 1, 1], [2, 1, 1], [3, 3], [1, 2, 3, 2]])
+def test_abs_sum_rank_one_gaussian_integers(oracle, M):
+    # A = u v^T with Gaussian-integer entries and even n: the addend of sign vector
+    # delta has modulus |prod v| |sum_i delta_i u_i|^n, an exact integer times |prod v|,
+    # summed here over every sign vector in Python integers.
+    rng = np.random.default_rng(sum(M) * 7 + len(M))
+    n = sum(M)
+    assert n % 2 == 0
+    u = rng.integers(-3, 4, len(M)) + 1j * rng.integers(-3, 4, len(M))
+    v = rng.integers(1, 4, n) + 1j * rng.integers(-2, 3, n)
+    ue = [complex(x) for x in np.repeat(u, M)]
+    tot = 0
+    for signs in product([1, -1], repeat=n - 1):
+        z = ue[0] + sum(sg * x for sg, x in zip(signs, ue[1:]))
+        re, im = int(z.real), int(z.imag)
+        tot += (re * re + im * im) ** (n // 2)
+    pv = math.sqrt(math.prod(int(x.real) ** 2 + int(x.imag) ** 2 for x in v))
+    expect = pv * float(Fraction(tot, 2 ** (n - 1)))
+    A = np.outer(u, v)
+    _, gab = oracle.perm_generalized(A, np.asarray(M, dtype=np.int32), with_abs=True)
+    _, ab = oracle.perm_glynn(expand_rows(A, M), with_abs=True)
+    assert rel(gab, expect) < 1e-13
+    assert rel(ab, expect) < 1e-13
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_abs_sum_generalized_equals_row_expanded(oracle, seed):
+    rng = np.random.default_rng(700 + seed)
+    n = int(rng.integers(4, 12))
+    M = np.bincount(rng.integers(0, max(2, n // 2), n))
+    M = M[M > 0].astype(np.int32)
+    A = rand_c(rng, len(M), n)
+    _, gab = oracle.perm_generalized(A, M, with_abs=True)
+    _, ab = oracle.perm_glynn(expand_rows(A, M), with_abs=True)
+    assert rel(gab, ab) < 1e-12
+    # the pivot choice does not change the multiset of addends either
+    for p in range(len(M)):
+        _, pab = oracle.perm_generalized(A, M, pivot=p, with_abs=True)
+        assert rel(pab, ab) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Eq. (ryser) with row multiplicities
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", range(5))
+def test_ryser_generalized_matches_definition(oracle, seed):
+    rng = np.random.default_rng(800 + seed)
+    n = int(rng.integers(2, 9))
+    M = np.bincount(rng.integers(0, max(2, n // 2 + 1), n))
+    M = M[M > 0].astype(np.int32)
+    A = rand_c(rng, len(M), n)
+    B = expand_rows(A, M)
+    ref = oracle.perm_bruteforce(B)
+    assert rel(oracle.perm_ryser_generalized(A, M), ref) < 1e-13
+    # column subsets of the transposed expanded matrix: the same permanent
+    assert rel(oracle.perm_ryser(np.ascontiguousarray(B.T)), ref) < 1e-13
+
+
+@pytest.mark.parametrize("M", [[4], [1, 1, 1, 1, 1], [2, 3], [3, 1, 2]])
+def test_ryser_generalized_ones_closed_forms(oracle, M):
+    # J_n: a subset with s of the n rows gives (-1)^{n-s} s^n, in C(n, s) ways; the
+    # sum is n! (the Stirling identity) and the magnitudes sum to sum_s C(n, s) s^n.
+    n = sum(M)
+    A = np.ones((len(M), n), dtype=complex)
+    v, ab = oracle.perm_ryser_generalized(A, M, with_abs=True)
+    assert v == math.factorial(n)
+    assert rel(ab, float(sum(math.comb(n, s) * s ** n for s in range(n + 1)))) < 1e-14
+
+
+def test_ryser_generalized_diagonal_and_zero_rows(oracle):
+    rng = np.random.default_rng(17)
+    d = rng.standard_normal(6) + 1j * rng.standard_normal(6)
+    assert rel(oracle.perm_ryser_generalized(np.diag(d), np.ones(6, dtype=np.int32)), np.prod(d)) < 1e-14
+    A = rand_c(rng, 4, 5)
+    M = np.array([2, 0, 3, 0], dtype=np.int32)
+    assert rel(oracle.perm_ryser_generalized(A, M), oracle.perm_bruteforce(expand_rows(A, M))) < 1e-13
 
 
 # ---------------------------------------------------------------------------
@@ -393,3 +511,105 @@ def test_oracle_sampler_matches_exact_distribution(oracle):
     tv *= 0.5
     # 35 outcomes, N = 2e4: the expected TV distance of an exact sampler is ~0.015
     assert tv < 0.03
+
+
+# ---------------------------------------------------------------------------
+# Non-uniform loss (Sec. 4): the lossy interferometer matrix T and its isometry
+# ---------------------------------------------------------------------------
+
+def _complete_unitary(V, seed=0):
+    # a 2m x 2m unitary whose first m columns are the isometry V
+    rng = np.random.default_rng(seed)
+    two_m, m = V.shape
+    Z = np.concatenate([V, rng.standard_normal((two_m, two_m - m)) + 1j * rng.standard_normal((two_m, two_m - m))],
+                       axis=1)
+    Q, R = np.linalg.qr(Z)
+    Q = Q * (np.diag(R) / np.abs(np.diag(R)))[None, :]
+    Q[:, :m] = V
+    return Q
+
+
+def _lossy_marginal(oracle, V, m, S, T):
+    # Eq. (bs_p) on a unitary completion of V, summed over the unmeasured modes
+    W = _complete_unitary(V)
+    n, kept = sum(S), sum(T)
+    return sum(oracle.bs_prob(W, list(S) + [0] * m, list(T) + list(H)) for H in patterns(m, n - kept))
+
+
+def test_contraction_isometry(oracle):
+    from paper_2309_07027_amd.inputs import haar_unitary
+    m = 5
+    U = haar_unitary(31, m)
+    eta = np.array([0.9, 0.5, 1.0, 0.2, 0.7])
+    for T in (U * np.sqrt(eta)[None, :], np.sqrt(eta)[:, None] * U, 0.8 * U, U):
+        V = oracle.contraction_isometry(T)
+        assert np.abs(V.conj().T @ V - np.eye(m)).max() < 1e-13
+        assert np.array_equal(V[:m], T)
+        R = V[m:]
+        assert np.abs(np.tril(R, -1)).max() == 0.0
+        assert (np.diag(R).real >= 0).all() and (np.diag(R).imag == 0).all()
+    # uniform loss: R^H R = (1 - eta) I, and R itself sqrt(1 - eta) I
+    V = oracle.contraction_isometry(np.sqrt(0.3) * U)
+    assert np.abs(V[m:] - np.sqrt(0.7) * np.eye(m)).max() < 1e-13
+    with pytest.raises(ValueError):
+        oracle.contraction_isometry(1.01 * U)
+
+
+@pytest.mark.parametrize("where", ["inputs", "outputs"])
+def test_lossy_matrix_marginal_matches_per_mode_loss(oracle, where):
+    # T = U diag(sqrt eta): each photon entering mode i survives with probability
+    # eta_i, then U.  T = diag(sqrt eta) U: U, then a photon leaving mode j is
+    # detected with probability eta_j.  Both closed forms against the exact law of
+    # the isometry [T; R] summed over the unmeasured modes.
+    from paper_2309_07027_amd.inputs import haar_unitary
+    m = 3
+    U = haar_unitary(44, m)
+    eta = np.array([0.8, 0.35, 0.6])
+    T = U * np.sqrt(eta)[None, :] if where == "inputs" else np.sqrt(eta)[:, None] * U
+    V = oracle.contraction_isometry(T)
+    S = [1, 1, 0]
+    n = sum(S)
+    total = 0.0
+    for kept in range(n + 1):
+        for Tp in patterns(m, kept):
+            got = _lossy_marginal(oracle, V, m, S, Tp)
+            cf = 0.0
+            if where == "inputs":
+                for Sp in product(*[range(s + 1) for s in S]):
+                    if sum(Sp) != kept:
+                        continue
+                    w = math.prod(math.comb(s, sp) * eta[i] ** sp * (1 - eta[i]) ** (s - sp)
+                                  for i, (s, sp) in enumerate(zip(S, Sp)))
+                    cf += w * oracle.bs_prob(U, list(Sp), list(Tp))
+            else:
+                for Tfull in patterns(m, n):
+                    if any(tf < t for tf, t in zip(Tfull, Tp)):
+                        continue
+                    w = math.prod(math.comb(tf, t) * eta[j] ** t * (1 - eta[j]) ** (tf - t)
+                                  for j, (tf, t) in enumerate(zip(Tfull, Tp)))
+                    cf += w * oracle.bs_prob(U, S, list(Tfull))
+            assert abs(got - cf) < 1e-13
+            total += got
+    assert abs(total - 1.0) < 1e-13
+
+
+def test_lossy_matrix_sampler_law(oracle):
+    from paper_2309_07027_amd.inputs import haar_unitary
+    m = 4
+    U = haar_unitary(45, m)
+    eta = np.array([0.9, 0.4, 0.7, 1.0])
+    T = U * np.sqrt(eta)[None, :]
+    V = oracle.contraction_isometry(T)
+    occ = [1, 1, 1, 0]
+    N = 20000
+    samples = oracle.cc_sample_lossy(T, occ, N, 321)
+    counts = {}
+    for s in samples:
+        counts[tuple(s)] = counts.get(tuple(s), 0) + 1
+    tv = 0.0
+    for kept in range(4):
+        for Tp in patterns(m, kept):
+            tv += abs(counts.get(Tp, 0) / N - _lossy_marginal(oracle, V, m, occ, Tp))
+    assert 0.5 * tv < 0.03
+    # the mean number of detected photons: sum of the occupied inputs' eta
+    assert abs(samples.sum(axis=1).mean() - eta[:3].sum()) < 4 * math.sqrt(3 * 0.25 / N)
