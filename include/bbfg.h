@@ -1,7 +1,7 @@
 /*
  * bbfg.h -- C ABI of the MI355X (gfx950) generalized BB/FG permanent library.
  *
- * Method: M. Morse et al., "High performance Boson Sampling simulation via
+ * Method: G. Morse et al., "High performance Boson Sampling simulation via
  * data-flow engines" (arXiv:2309.07027).
  *   - Eq. (bbfg): the Balasubramanian-Bax-Franklin-Glynn formula with column
  *     sums over rows (Sec. 2).
@@ -58,8 +58,9 @@ typedef enum {
     BBFG_ERANGE = -2,   /* size beyond the supported maximum */
     BBFG_ENOMEM = -3,   /* device or pinned host allocation failed */
     BBFG_EDEVICE = -4,  /* HIP runtime error (no device, launch failure, ...) */
-    BBFG_EBUSY = -5,    /* server job not finished yet */
-    BBFG_ENOTFOUND = -6 /* unknown server job id */
+    BBFG_EBUSY = -5,     /* server job not finished yet */
+    BBFG_ENOTFOUND = -6, /* unknown server job id */
+    BBFG_ECANCELED = -7  /* server job cancelled before it finished */
 } bbfg_status;
 
 /* BBFG_MINORS names the batched leave-one-column-out walks (FP64) in the
@@ -193,15 +194,20 @@ int perm_bbfg_cols(const bbfg_c128 *A, int32_t n_rows, const int32_t *row_mult, 
  *   n_cols    1 <= n_cols <= BBFG_MAX_N.
  *   out       n_cols bbfg_c128, host or device:
  *             out[l] = perm(A without column l, row_mult).
+ *   rel_err_est  nullable, n_cols doubles (host): estimated relative error of
+ *             out[l], kappa_l * u * (n + sqrt(Q)) with kappa_l the sum of
+ *             |addend| of minor l over |out[l]|.  The magnitude sums are taken
+ *             at every Gray position of sums up to 2^20 addends, and at every
+ *             257th position (weighted by 257) of longer ones.
  *
- * FP64 with double-double reduction; no error estimate is formed (the
- * magnitude sums are not accumulated).  n_cols = 1 gives the empty permanent 1.
+ * FP64 with double-double reduction.  n_cols = 1 gives the empty permanent 1.
  * The walk is split to fill the device (as perm_bbfg splits a lone permanent),
  * so values may differ in the last bits from the minors the sampler forms.
  * Errors: EINVAL (NULL pointer, negative multiplicity, sum != n_cols - 1),
  * ERANGE (n_cols > BBFG_MAX_N), ENOMEM/EDEVICE.
  */
-int perm_minors(const bbfg_c128 *A, int32_t n_rows, const int32_t *row_mult, int32_t n_cols, bbfg_c128 *out);
+int perm_minors(const bbfg_c128 *A, int32_t n_rows, const int32_t *row_mult, int32_t n_cols, bbfg_c128 *out,
+                double *rel_err_est);
 
 /* Device time (ms) of the last perm_batch or perm_minors on this thread: the
  * walk kernel when launched directly, the whole replayed graph otherwise. */
@@ -264,13 +270,43 @@ int bbfg_batch_unit_length(int32_t n_cols, int32_t precision, uint64_t *unit_len
 int bs_sample(const bbfg_c128 *U, int32_t m, const int32_t *input_occupation, int32_t n_samples,
               double loss, uint64_t seed, int32_t *out_occupation, bbfg_info *info);
 
+/*
+ * bs_sample_lossy -- Clifford & Clifford sampling through a lossy
+ * interferometer with non-uniform losses (Sec. 4: the losses stay in the
+ * interferometer matrix, which is then no longer unitary, and the sampler runs
+ * on twice the modes, sampling only the first half).
+ *
+ *   T                 m x m matrix of the lossy interferometer (row-major),
+ *                     host or device: a contraction, T^H T <= I (singular
+ *                     values at most 1).  Per-mode transmissions eta_i at the
+ *                     inputs are T = U diag(sqrt(eta)); at the outputs
+ *                     T = diag(sqrt(eta)) U; uniform loss is sqrt(eta) U.
+ *   m, input_occupation, n_samples, seed, out_occupation, info
+ *                     as bs_sample (1 <= m <= 128); info->rel_err_est as
+ *                     bs_sample.
+ *
+ * The photons enter the first m of 2m modes of the isometry [T; R] (R the
+ * upper-triangular Cholesky factor of I - T^H T, built on the host); all 2m
+ * rows are candidate outputs and the first m are reported.  Every R with
+ * R^H R = I - T^H T gives the same law on the first m modes, so for T =
+ * sqrt(eta) U the law is that of bs_sample with loss 1 - eta, though not the
+ * same samples (bs_sample uses the block dilation).
+ * Errors: as bs_sample; BBFG_EINVAL also when T is not a contraction (a pivot
+ * of I - T^H T below -1e-10).
+ */
+int bs_sample_lossy(const bbfg_c128 *T, int32_t m, const int32_t *input_occupation, int32_t n_samples,
+                    uint64_t seed, int32_t *out_occupation, bbfg_info *info);
+
 /* ---------------------------------------------------------------------------
- * Sampling server: continuous batching of Clifford & Clifford jobs.
- * A background host thread admits queued jobs while the device-memory budget
- * and the active-job limit allow, keeps each admitted job's matrix and partial
- * samples resident on the device, and in every iteration evaluates the current
- * step's permanents of ALL active jobs in one batched launch.  A job's samples
- * are identical to bs_sample with the same arguments.
+ * Sampling server: continuous batching of Clifford & Clifford jobs.  Sec. 4
+ * scales the sampler by running independent samplers side by side (one MPI
+ * process per accelerator) and gathering their samples; on one GPU the
+ * samplers share the device instead.  A background host thread admits queued
+ * jobs while the device-memory budget and the active-job limit allow, keeps
+ * each admitted job's matrix and partial samples resident on the device, and
+ * in every iteration evaluates the current step's permanents of ALL active
+ * jobs in one batched launch.  A job's samples are identical to bs_sample (or
+ * bs_sample_lossy) with the same arguments.
  * ------------------------------------------------------------------------- */
 typedef struct bbfg_server bbfg_server;
 
@@ -283,11 +319,28 @@ int bs_server_create(size_t hbm_budget_bytes, int32_t max_active_jobs, bbfg_serv
 int bs_server_submit(bbfg_server *srv, const bbfg_c128 *U, int32_t m, const int32_t *input_occupation,
                      int32_t n_samples, double loss, uint64_t seed, uint64_t *job_id);
 
+/* Queue a job through the lossy interferometer matrix T (arguments and
+ * samples as bs_sample_lossy; T is copied and validated before the call
+ * returns).  Errors: BBFG_EINVAL (also a T that is not a contraction),
+ * BBFG_ERANGE. */
+int bs_server_submit_lossy(bbfg_server *srv, const bbfg_c128 *T, int32_t m, const int32_t *input_occupation,
+                           int32_t n_samples, uint64_t seed, uint64_t *job_id);
+
 /* Non-blocking: BBFG_EBUSY while the job runs; on completion copies
- * n_samples x m occupations to out_occupation (host) and the job's latency
- * (completion - submission, seconds) to latency_s (nullable), then forgets the
- * job.  Errors: BBFG_ENOTFOUND, BBFG_EDEVICE (the job failed). */
-int bs_server_poll(bbfg_server *srv, uint64_t job_id, int32_t *out_occupation, double *latency_s);
+ * n_samples x m occupations to out_occupation (host), the job's latency
+ * (completion - submission, seconds) to latency_s (nullable) and its error
+ * estimate to err_est (nullable; as bbfg_info.rel_err_est of bs_sample), then
+ * forgets the job.  Errors: BBFG_ENOTFOUND, BBFG_ECANCELED (the job was
+ * cancelled; it is forgotten), BBFG_EDEVICE (the job failed). */
+int bs_server_poll(bbfg_server *srv, uint64_t job_id, int32_t *out_occupation, double *latency_s,
+                   double *err_est);
+
+/* Cancels a job.  A queued job is dropped at once; an active one leaves the
+ * device at the end of its current step (its memory and slot are freed for
+ * other jobs then); in both cases a later poll returns BBFG_ECANCELED.  A
+ * finished job that was not polled yet is forgotten with its samples.
+ * Non-blocking.  Errors: BBFG_EINVAL, BBFG_ENOTFOUND. */
+int bs_server_cancel(bbfg_server *srv, uint64_t job_id);
 
 /* Blocks until all submitted jobs are finished (polled or not). */
 int bs_server_drain(bbfg_server *srv);
@@ -299,6 +352,7 @@ int bs_server_destroy(bbfg_server *srv);
 typedef struct {
     uint64_t jobs_submitted, jobs_done, iterations, samples_done;
     uint64_t max_active, max_queued;
+    uint64_t jobs_cancelled;
     double busy_s; /* worker time spent advancing samples (host preparation + device) */
     double host_s; /* part of busy_s spent preparing steps on the host (plans, metadata, launches) */
     double wait_s; /* part of busy_s spent waiting for the device to finish a step */

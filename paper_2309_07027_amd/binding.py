@@ -21,6 +21,7 @@ BBFG_ENOMEM = -3
 BBFG_EDEVICE = -4
 BBFG_EBUSY = -5
 BBFG_ENOTFOUND = -6
+BBFG_ECANCELED = -7
 BBFG_FP64 = 0
 BBFG_FP32 = 1
 BBFG_MINORS = 2
@@ -58,7 +59,8 @@ class PlanSummary(ctypes.Structure):
 class ServerStats(ctypes.Structure):
     _fields_ = [("jobs_submitted", ctypes.c_uint64), ("jobs_done", ctypes.c_uint64),
                 ("iterations", ctypes.c_uint64), ("samples_done", ctypes.c_uint64),
-                ("max_active", ctypes.c_uint64), ("max_queued", ctypes.c_uint64), ("busy_s", ctypes.c_double),
+                ("max_active", ctypes.c_uint64), ("max_queued", ctypes.c_uint64),
+                ("jobs_cancelled", ctypes.c_uint64), ("busy_s", ctypes.c_double),
                 ("host_s", ctypes.c_double), ("wait_s", ctypes.c_double)]
 
     def as_dict(self):
@@ -80,16 +82,20 @@ SIGNATURES = {
     "bbfg_set_cache_limits": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_uint64]),
     "perm_bbfg": (ctypes.c_int, [_P, _I32, _PI32, _I32, _P, ctypes.POINTER(Info)]),
     "perm_batch": (ctypes.c_int, [_I32, _P, _PI64, _PI32, _PI32, _PI64, _PI32, _I32, _P, _PD]),
-    "perm_minors": (ctypes.c_int, [_P, _I32, _PI32, _I32, _P]),
+    "perm_minors": (ctypes.c_int, [_P, _I32, _PI32, _I32, _P, _PD]),
     "perm_bbfg_cols": (ctypes.c_int, [_P, _I32, _PI32, _I32, _PI32, _P, ctypes.POINTER(Info)]),
     "perm_batch_last_kernel_ms": (ctypes.c_double, []),
     "perm_batch_last_was_graph": (ctypes.c_int, []),
     "bs_sample": (ctypes.c_int, [_P, _I32, _PI32, _I32, ctypes.c_double, ctypes.c_uint64, _PI32,
                                  ctypes.POINTER(Info)]),
+    "bs_sample_lossy": (ctypes.c_int, [_P, _I32, _PI32, _I32, ctypes.c_uint64, _PI32, ctypes.POINTER(Info)]),
     "bs_server_create": (ctypes.c_int, [ctypes.c_size_t, _I32, ctypes.POINTER(_P)]),
     "bs_server_submit": (ctypes.c_int, [_P, _P, _I32, _PI32, _I32, ctypes.c_double, ctypes.c_uint64,
                                         ctypes.POINTER(ctypes.c_uint64)]),
-    "bs_server_poll": (ctypes.c_int, [_P, ctypes.c_uint64, _PI32, _PD]),
+    "bs_server_submit_lossy": (ctypes.c_int, [_P, _P, _I32, _PI32, _I32, ctypes.c_uint64,
+                                              ctypes.POINTER(ctypes.c_uint64)]),
+    "bs_server_poll": (ctypes.c_int, [_P, ctypes.c_uint64, _PI32, _PD, _PD]),
+    "bs_server_cancel": (ctypes.c_int, [_P, ctypes.c_uint64]),
     "bs_server_drain": (ctypes.c_int, [_P]),
     "bs_server_destroy": (ctypes.c_int, [_P]),
     "bs_server_stats": (ctypes.c_int, [_P, ctypes.POINTER(ServerStats)]),
@@ -253,15 +259,17 @@ def perm_bbfg_cols(A, row_mult, col_mult, with_info: bool = False):
     return (complex(out[0]), info.as_dict()) if with_info else complex(out[0])
 
 
-def perm_minors(A, M):
+def perm_minors(A, M, with_err: bool = False):
     """[perm(A without column l, M) for l in range(n_cols)] (host numpy complex128);
-    sum(M) == n_cols - 1.  A may be a torch cuda tensor."""
+    sum(M) == n_cols - 1.  A may be a torch cuda tensor.  with_err: also the
+    per-minor relative error estimates."""
     ptr, keep, shape = _cmat_ptr(A)
     m, pm = _i32(M)
     out = np.zeros(shape[1], dtype=np.complex128)
-    _check(lib().perm_minors(ptr, shape[0], pm, shape[1], ctypes.c_void_p(out.ctypes.data)))
+    err = np.zeros(shape[1], dtype=np.float64)
+    _check(lib().perm_minors(ptr, shape[0], pm, shape[1], ctypes.c_void_p(out.ctypes.data), err.ctypes.data_as(_PD)))
     del keep
-    return out
+    return (out, err) if with_err else out
 
 
 def batch_last_kernel_ms() -> float:
@@ -285,6 +293,19 @@ def bs_sample(U, input_occupation, n_samples: int, loss: float = 0.0, seed: int 
     return (out, info.as_dict()) if with_info else out
 
 
+def bs_sample_lossy(T, input_occupation, n_samples: int, seed: int = 0, with_info: bool = False):
+    """Samples through the lossy interferometer matrix T (a contraction): (n_samples, m) int32."""
+    ptr, keep, shape = _cmat_ptr(T)
+    m = shape[0]
+    occ, po = _i32(input_occupation)
+    out = np.zeros((n_samples, m), dtype=np.int32)
+    info = Info()
+    _check(lib().bs_sample_lossy(ptr, m, po, int(n_samples), ctypes.c_uint64(seed & (2**64 - 1)),
+                                 out.ctypes.data_as(_PI32), ctypes.byref(info)))
+    del keep
+    return (out, info.as_dict()) if with_info else out
+
+
 class Server:
     """Continuous-batching sampling server (bs_server_*)."""
 
@@ -304,17 +325,34 @@ class Server:
         del keep
         return jid.value
 
-    def poll(self, job_id: int):
-        """None while running, else (samples, latency_s)."""
+    def submit_lossy(self, T, input_occupation, n_samples: int, seed: int = 0) -> int:
+        ptr, keep, shape = _cmat_ptr(T)
+        occ, po = _i32(input_occupation)
+        jid = ctypes.c_uint64()
+        _check(lib().bs_server_submit_lossy(self._h, ptr, shape[0], po, int(n_samples),
+                                            ctypes.c_uint64(seed & (2**64 - 1)), ctypes.byref(jid)))
+        self._m[jid.value] = (int(n_samples), shape[0])
+        del keep
+        return jid.value
+
+    def poll(self, job_id: int, with_err: bool = False):
+        """None while running, else (samples, latency_s) -- with_err: (samples,
+        latency_s, err_est).  A cancelled job raises BBFGError (BBFG_ECANCELED)."""
         ns, m = self._m.get(job_id, (0, 1))
         out = np.zeros((max(ns, 1), m), dtype=np.int32)
         lat = ctypes.c_double()
-        rc = lib().bs_server_poll(self._h, ctypes.c_uint64(job_id), out.ctypes.data_as(_PI32), ctypes.byref(lat))
+        err = ctypes.c_double()
+        rc = lib().bs_server_poll(self._h, ctypes.c_uint64(job_id), out.ctypes.data_as(_PI32), ctypes.byref(lat),
+                                  ctypes.byref(err))
         if rc == BBFG_EBUSY:
             return None
-        _check(rc)
         self._m.pop(job_id, None)
-        return out[:ns], lat.value
+        _check(rc)
+        return (out[:ns], lat.value, err.value) if with_err else (out[:ns], lat.value)
+
+    def cancel(self, job_id: int):
+        """Cancel a queued or active job (its later poll raises BBFG_ECANCELED)."""
+        _check(lib().bs_server_cancel(self._h, ctypes.c_uint64(job_id)))
 
     def drain(self):
         _check(lib().bs_server_drain(self._h))

@@ -225,7 +225,8 @@ try {
 }
 BBFG_API_CATCH
 
-int perm_minors(const bbfg_c128* A, int32_t n_rows, const int32_t* row_mult, int32_t n_cols, bbfg_c128* out)
+int perm_minors(const bbfg_c128* A, int32_t n_rows, const int32_t* row_mult, int32_t n_cols, bbfg_c128* out,
+                double* rel_err_est)
 try {
     if (!out) return set_error(BBFG_EINVAL, "out is NULL");
     if (n_cols < 1) return set_error(BBFG_EINVAL, "n_cols = %d < 1", n_cols);
@@ -235,6 +236,7 @@ try {
     std::vector<double> res(2 * (size_t)n_cols, 0.0);
     if (n_cols == 1) {
         res[0] = 1.0;  // the empty permanent
+        if (rel_err_est) rel_err_est[0] = 0.0;
         return write_results(out, res.data(), 1);
     }
     Context* c = nullptr;
@@ -260,13 +262,14 @@ try {
     add_minor_items(proto, cols.data(), keep, items, 0, slot.data());
     size_t nres = 0;
     for (auto& it : items) nres += (size_t)it.targets;
-    std::vector<double> r2(2 * nres);
+    std::vector<double> r2(2 * nres), d2(2 * nres);
     RunResult rr;
-    BBFG_TRY(run_perms(*c, items, 0, false, r2.data(), nullptr, &rr));
+    BBFG_TRY(run_perms(*c, items, 0, false, r2.data(), d2.data(), &rr));
     t_batch_kernel_ms = rr.kernel_ms;
     for (int32_t l = 0; l < n_cols; ++l) {
         res[2 * (size_t)l] = r2[2 * (size_t)slot[(size_t)l]];
         res[2 * (size_t)l + 1] = r2[2 * (size_t)slot[(size_t)l] + 1];
+        if (rel_err_est) rel_err_est[l] = d2[2 * (size_t)slot[(size_t)l]];
     }
     return write_results(out, res.data(), (size_t)n_cols);
 }

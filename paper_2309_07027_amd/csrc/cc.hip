@@ -40,14 +40,17 @@ __global__ __launch_bounds__(kCCThreads) void cc_weights_kernel(const CCStep* __
                                                                 const int32_t* __restrict__ pi,
                                                                 const uint32_t* __restrict__ slot,
                                                                 const double* __restrict__ minors,
-                                                                int32_t* __restrict__ drawn, double* __restrict__ wsum)
+                                                                const double* __restrict__ minor_err,
+                                                                int32_t* __restrict__ drawn, double* __restrict__ wsum,
+                                                                double* __restrict__ tv_est)
 {
     const CCStep st = steps[blockIdx.x];
     __shared__ double w[kCCThreads];
+    __shared__ double dw[kCCThreads];
     const int32_t* p = pi + st.pi_off;
     for (int r = threadIdx.x; r < st.rows; r += kCCThreads) {
         const double* arow = st.A + 2 * (size_t)r * st.n;
-        double sr = 0.0, si = 0.0;
+        double sr = 0.0, si = 0.0, e = 0.0;
         if (st.k == 1) {
             sr = arow[2 * p[0]];
             si = arow[2 * p[0] + 1];
@@ -61,14 +64,20 @@ __global__ __launch_bounds__(kCCThreads) void cc_weights_kernel(const CCStep* __
                 sr = __builtin_fma(-ai, mi, sr);
                 si = __builtin_fma(ar, mi, si);
                 si = __builtin_fma(ai, mr, si);
+                e += __builtin_sqrt(ar * ar + ai * ai) * __builtin_sqrt(mr * mr + mi * mi) * minor_err[2 * q];
             }
         }
         w[r] = __builtin_fma(sr, sr, si * si);
+        dw[r] = e * (2.0 * __builtin_sqrt(w[r]) + e);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double total = 0.0;
-        for (int r = 0; r < st.rows; ++r) total += w[r];
+        double total = 0.0, dtotal = 0.0;
+        for (int r = 0; r < st.rows; ++r) {
+            total += w[r];
+            dtotal += dw[r];
+        }
+        tv_est[blockIdx.x] = total > 0.0 ? dtotal / total : 0.0;
         const double target = st.u * total;
         double run = 0.0;
         int choice = -1;
@@ -102,10 +111,12 @@ hipError_t launch_build_job_matrix(const double* U, int m, const int32_t* cols, 
 }
 
 hipError_t launch_cc_weights(uint32_t nsteps, const CCStep* steps, const int32_t* pi, const uint32_t* slot,
-                             const double* minors, int32_t* drawn, double* wsum, hipStream_t s)
+                             const double* minors, const double* minor_err, int32_t* drawn, double* wsum,
+                             double* tv_est, hipStream_t s)
 {
     if (nsteps == 0) return hipSuccess;
-    hipLaunchKernelGGL(cc_weights_kernel, dim3(nsteps), dim3(kCCThreads), 0, s, steps, pi, slot, minors, drawn, wsum);
+    hipLaunchKernelGGL(cc_weights_kernel, dim3(nsteps), dim3(kCCThreads), 0, s, steps, pi, slot, minors, minor_err,
+                       drawn, wsum, tv_est);
     return hipGetLastError();
 }
 

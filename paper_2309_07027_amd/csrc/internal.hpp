@@ -65,8 +65,19 @@ struct PermDesc {
     uint32_t res_base;       // index of the first result
     uint32_t col_pow;        // every one of the n (distinct) columns has multiplicity col_pow
                              //   (Eq. bbfgrepeated): the product is (prod_j c_j)^col_pow
-    uint32_t pad;
+    uint32_t mag_stride;     // leave-one-column-out walks: the magnitude sum of each target is
+                             //   taken over the positions lin = 0 mod mag_stride of a lane's range
+                             //   and weighted by mag_stride (1: every position)
 };
+
+// Leave-one-column-out walks accumulate the magnitudes of each target's
+// addends (for the error estimate) at every position of sums up to
+// kMagExactAddends addends, and at every kMagStride-th position of longer ones
+// (at least 4096 samples per target).  The stride is a prime above every Gray
+// radix (M + 1 <= 49), so the sampled positions do not follow the digit
+// pattern; a sampled step leaves the walk's inner loop, so it is kept rare.
+constexpr uint64_t kMagExactAddends = uint64_t(1) << 20;
+constexpr uint32_t kMagStride = 257;
 
 // Leave-one-column-out walks over K columns cover the targets in groups of
 // minor_group(K): one group keeps K column sums, G prefix products and G
@@ -87,6 +98,14 @@ constexpr int minor_group(int K)
     if (gmax > K) gmax = K;
     const int groups = (K + gmax - 1) / gmax;
     return (K + groups - 1) / groups;
+}
+
+// Most targets of one leave-one-column-out walk over at most KMAX columns.
+constexpr int max_minor_group(int KMAX)
+{
+    int g = 1;
+    for (int K = 2; K <= KMAX; ++K) g = minor_group(K) > g ? minor_group(K) : g;
+    return g;
 }
 
 constexpr uint32_t kUnitChunkLog2 = 6;

@@ -462,6 +462,7 @@ int run_perms(Context& c, Workspace& w, std::vector<PermItem>& items, int f32, b
         d.targets = (uint32_t)items[i].targets;
         d.res_base = res_base[i];
         d.col_pow = items[i].col_pow >= 2 ? (uint32_t)items[i].col_pow : 1u;
+        d.mag_stride = (items[i].targets > 0 && p.n_addends > kMagExactAddends) ? kMagStride : 1u;
         for (uint64_t t = 0; t < stride_of(items[i]); ++t) hri[res_base[i] + t] = (uint32_t)i;
         PrepItem& q = hp[i];
         std::memset(&q, 0, sizeof q);

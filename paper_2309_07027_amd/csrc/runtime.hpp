@@ -228,7 +228,9 @@ struct RunResult {
 // Evaluates items (all n >= 1).  The (re, im) results stay in c.results (item
 // order; an item with targets = G has G consecutive results) and, when out_host
 // is not null, are copied to out_host[2*i]; the diagnostics (err_est, kappa) to
-// diag_host[2*i] (zero for minor items, whose magnitude sums are not formed).  With sync = false nothing is
+// diag_host[2*i] (for minor items from the sampled magnitude sums, see
+// walk_minors_unit).  The device copy of the diagnostics follows the results:
+// w.results + 2 * (number of results).  With sync = false nothing is
 // copied back and the stream is not synchronised (the caller queues more work
 // that reads c.results).  single = true uses the one-permanent launch.
 // use_graph = true captures a layout into a hipGraph the second time it is

@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <complex>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -78,6 +79,7 @@ int cc_job_init(Context& c, CCJob& job, const double* U, bool U_on_device, int m
     job.started = job.finished = 0;
     job.kernel_ms = 0.0;
     job.n_addends = 0;
+    job.tv_max = 0.0;
     if (job.n == 0) return BBFG_OK;
     // device: [U (m x m), when on the host | cols (n int32)], then A
     const size_t ubytes = U_on_device ? 0 : 16 * (size_t)m * (size_t)m;
@@ -103,11 +105,84 @@ int cc_job_init(Context& c, CCJob& job, const double* U, bool U_on_device, int m
     return BBFG_OK;
 }
 
+int cc_lossy_job_matrix(const double* T, int m, const int32_t* occ, std::vector<double>& A)
+{
+    using cd = std::complex<double>;
+    const cd* t = reinterpret_cast<const cd*>(T);
+    // G = I - T^H T (Hermitian); overwritten by the trailing updates below
+    std::vector<cd> G((size_t)m * (size_t)m), R((size_t)m * (size_t)m, cd(0.0, 0.0));
+    for (int j = 0; j < m; ++j)
+        for (int k = j; k < m; ++k) {
+            cd acc(0.0, 0.0);
+            for (int i = 0; i < m; ++i) acc += std::conj(t[(size_t)i * m + j]) * t[(size_t)i * m + k];
+            G[(size_t)j * m + k] = (j == k ? cd(1.0, 0.0) : cd(0.0, 0.0)) - acc;
+        }
+    // right-looking Cholesky of the upper triangle: row j of R from the pivot,
+    // then the trailing block loses the outer product of that row
+    constexpr double kTol = 1e-10;
+    for (int j = 0; j < m; ++j) {
+        const double d = G[(size_t)j * m + j].real();
+        if (d < -kTol) return set_error(BBFG_EINVAL, "T is not a contraction: pivot %d of I - T^H T is %g", j, d);
+        if (d <= 0.0) continue;  // a zero pivot (lossless direction) leaves row j of R at zero
+        const double rjj = std::sqrt(d);
+        R[(size_t)j * m + j] = rjj;
+        for (int k = j + 1; k < m; ++k) R[(size_t)j * m + k] = G[(size_t)j * m + k] / rjj;
+        for (int k = j + 1; k < m; ++k)
+            for (int l = k; l < m; ++l) G[(size_t)k * m + l] -= std::conj(R[(size_t)j * m + k]) * R[(size_t)j * m + l];
+    }
+    std::vector<int> cols;
+    for (int i = 0; i < m; ++i)
+        for (int q = 0; q < occ[i]; ++q) cols.push_back(i);
+    const size_t n = cols.size();
+    A.assign(2 * (size_t)(2 * m) * n, 0.0);
+    for (int r = 0; r < 2 * m; ++r)
+        for (size_t b = 0; b < n; ++b) {
+            const cd x = r < m ? t[(size_t)r * m + cols[b]] : R[(size_t)(r - m) * m + cols[b]];
+            A[2 * ((size_t)r * n + b)] = x.real();
+            A[2 * ((size_t)r * n + b) + 1] = x.imag();
+        }
+    return BBFG_OK;
+}
+
+int cc_job_init_matrix(Context& c, CCJob& job, const double* A_host, int rows, int m, const int32_t* occ,
+                       int n_samples, uint64_t seed, bool stage_pinned)
+{
+    (void)c;
+    hipStream_t s = current_stream();
+    job.m = m;
+    job.loss = 0.0;
+    job.rows = rows;
+    job.seed = seed;
+    job.n_samples = n_samples;
+    job.cols.clear();
+    for (int i = 0; i < m; ++i)
+        for (int t = 0; t < occ[i]; ++t) job.cols.push_back(i);
+    job.n = (int)job.cols.size();
+    job.samples.assign((size_t)n_samples, CCSample());
+    job.out.assign((size_t)n_samples * (size_t)m, 0);
+    job.started = job.finished = 0;
+    job.kernel_ms = 0.0;
+    job.n_addends = 0;
+    job.tv_max = 0.0;
+    if (job.n == 0) return BBFG_OK;
+    const size_t bytes = 16 * (size_t)rows * (size_t)job.n;
+    BBFG_TRY(job.A.ensure(bytes));
+    if (stage_pinned) {
+        BBFG_TRY(job.host_in.ensure(bytes));
+        std::memcpy(job.host_in.p, A_host, bytes);
+        BBFG_HIP(hipMemcpyAsync(job.A.p, job.host_in.p, bytes, hipMemcpyHostToDevice, s));
+    } else {
+        BBFG_HIP(hipMemcpyAsync(job.A.p, A_host, bytes, hipMemcpyHostToDevice, s));
+    }
+    return BBFG_OK;
+}
+
 void cc_start_sample(CCJob& job, int s)
 {
     CCSample& S = job.samples[(size_t)s];
     S.key = splitmix64_draw(job.seed, (uint64_t)s);
     S.k = 1;
+    S.tv = 0.0;
     S.prefix.clear();
     S.pi.resize((size_t)job.n);
     for (int b = 0; b < job.n; ++b) S.pi[(size_t)b] = b;
@@ -127,6 +202,7 @@ void finish_sample(CCJob& job, int s)
     for (int i = 0; i < job.m; ++i) o[i] = 0;
     for (int32_t r : S.prefix)
         if (r < job.m) o[r]++;
+    job.tv_max = std::max(job.tv_max, S.tv);
     job.finished++;
 }
 
@@ -232,6 +308,7 @@ int cc_step_begin(Context& c, Workspace& w, std::vector<ActiveSample>& act, CCPe
     const size_t o_slot = L.add(sizeof(uint32_t) * std::max<size_t>(1, slots.size()));
     const size_t o_drawn = L.add(sizeof(int32_t) * steps.size());
     const size_t o_wsum = L.add(sizeof(double) * steps.size());
+    const size_t o_tv = L.add(sizeof(double) * steps.size());
     BBFG_TRY(w.cc_hmeta.ensure(L.size));
     BBFG_TRY(w.cc_meta.ensure(L.size));
     char* H = w.cc_hmeta.as<char>();
@@ -240,13 +317,16 @@ int cc_step_begin(Context& c, Workspace& w, std::vector<ActiveSample>& act, CCPe
     std::memcpy(H + o_pi, pis.data(), sizeof(int32_t) * pis.size());
     if (!slots.empty()) std::memcpy(H + o_slot, slots.data(), sizeof(uint32_t) * slots.size());
     BBFG_HIP(hipMemcpyAsync(D, H, o_drawn, hipMemcpyHostToDevice, s));
+    // the minors' diagnostics follow their nres results (run_perms)
     BBFG_HIP(launch_cc_weights((uint32_t)steps.size(), reinterpret_cast<const CCStep*>(D + o_steps),
                                reinterpret_cast<const int32_t*>(D + o_pi),
                                reinterpret_cast<const uint32_t*>(D + o_slot), w.results.as<double>(),
-                               reinterpret_cast<int32_t*>(D + o_drawn), reinterpret_cast<double*>(D + o_wsum), s));
+                               w.results.as<double>() + 2 * nres, reinterpret_cast<int32_t*>(D + o_drawn),
+                               reinterpret_cast<double*>(D + o_wsum), reinterpret_cast<double*>(D + o_tv), s));
     BBFG_HIP(hipMemcpyAsync(H + o_drawn, D + o_drawn, L.size - o_drawn, hipMemcpyDeviceToHost, s));
     BBFG_HIP(hipEventRecord(w.done, s));
     p.o_drawn = o_drawn;
+    p.o_tv = o_tv;
     p.queued = true;
     return BBFG_OK;
 }
@@ -262,10 +342,12 @@ int cc_step_end(Workspace& w, std::vector<ActiveSample>& act, CCPending& p, doub
         *kernel_ms += ms;
     }
     const int32_t* drawn = reinterpret_cast<const int32_t*>(w.cc_hmeta.as<char>() + p.o_drawn);
+    const double* tv = reinterpret_cast<const double*>(w.cc_hmeta.as<char>() + p.o_tv);
     for (size_t i = 0; i < p.act_of_step.size(); ++i) {
         ActiveSample& a = act[p.act_of_step[i]];
         CCSample& S = a.job->samples[(size_t)a.s];
         S.prefix.push_back(drawn[i]);
+        S.tv += tv[i];
         S.k++;
         if (S.k > a.job->n) finish_sample(*a.job, a.s);
     }
@@ -290,6 +372,34 @@ int cc_step(Context& c, std::vector<ActiveSample>& act, double* kernel_ms, uint6
 
 using namespace bbfg;
 
+namespace {
+
+// Every sample of a job, in lock-step waves of at most 1024 samples.
+int run_job(Context& c, CCJob& job, int32_t* out_occupation, bbfg_info* info)
+{
+    constexpr int kWaveSamples = 1024;
+    double kms = 0.0;
+    uint64_t adds = 0;
+    for (int s0 = 0; s0 < job.n_samples; s0 += kWaveSamples) {
+        const int s1 = std::min(job.n_samples, s0 + kWaveSamples);
+        std::vector<ActiveSample> act;
+        for (int s = s0; s < s1; ++s) {
+            cc_start_sample(job, s);
+            act.push_back({&job, s});
+        }
+        for (int k = 1; k <= job.n; ++k) BBFG_TRY(cc_step(c, act, &kms, &adds));
+    }
+    std::memcpy(out_occupation, job.out.data(), sizeof(int32_t) * job.out.size());
+    if (info) {
+        info->kernel_ms = kms;
+        info->n_addends = adds;
+        info->rel_err_est = job.tv_max;
+    }
+    return BBFG_OK;
+}
+
+}  // namespace
+
 extern "C" int bs_sample(const bbfg_c128* U, int32_t m, const int32_t* input_occupation, int32_t n_samples,
                          double loss, uint64_t seed, int32_t* out_occupation, bbfg_info* info)
 try {
@@ -309,24 +419,37 @@ try {
     CCJob job;
     BBFG_TRY(cc_job_init(*c, job, reinterpret_cast<const double*>(U), is_device_ptr(U), m, input_occupation, n_samples,
                          loss, seed));
-    // samples advance in lock-step, in waves of at most kWaveSamples
-    constexpr int kWaveSamples = 1024;
-    double kms = 0.0;
-    uint64_t adds = 0;
-    for (int s0 = 0; s0 < n_samples; s0 += kWaveSamples) {
-        const int s1 = std::min(n_samples, s0 + kWaveSamples);
-        std::vector<ActiveSample> act;
-        for (int s = s0; s < s1; ++s) {
-            cc_start_sample(job, s);
-            act.push_back({&job, s});
-        }
-        for (int k = 1; k <= job.n; ++k) BBFG_TRY(cc_step(*c, act, &kms, &adds));
+    return run_job(*c, job, out_occupation, info);
+}
+BBFG_API_CATCH
+
+extern "C" int bs_sample_lossy(const bbfg_c128* T, int32_t m, const int32_t* input_occupation, int32_t n_samples,
+                               uint64_t seed, int32_t* out_occupation, bbfg_info* info)
+try {
+    // the lossy bounds (2m candidate rows)
+    BBFG_TRY(cc_validate(T, m, input_occupation, n_samples, 0.5));
+    if (n_samples > 0 && !out_occupation) return set_error(BBFG_EINVAL, "out_occupation is NULL");
+    std::vector<double> Th(2 * (size_t)m * (size_t)m);
+    if (is_device_ptr(T)) {
+        BBFG_HIP(hipMemcpy(Th.data(), T, sizeof(double) * Th.size(), hipMemcpyDeviceToHost));
+    } else {
+        std::memcpy(Th.data(), T, sizeof(double) * Th.size());
     }
-    std::memcpy(out_occupation, job.out.data(), sizeof(int32_t) * job.out.size());
-    if (info) {
-        info->kernel_ms = kms;
-        info->n_addends = adds;
+    std::vector<double> A;
+    BBFG_TRY(cc_lossy_job_matrix(Th.data(), m, input_occupation, A));
+    if (info) std::memset(info, 0, sizeof *info);
+    if (n_samples == 0) return BBFG_OK;
+    int64_t n = 0;
+    for (int i = 0; i < m; ++i) n += input_occupation[i];
+    if (n == 0) {
+        std::memset(out_occupation, 0, sizeof(int32_t) * (size_t)n_samples * (size_t)m);
+        return BBFG_OK;
     }
-    return BBFG_OK;
+    Context* c = nullptr;
+    BBFG_TRY(get_context(&c));
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    CCJob job;
+    BBFG_TRY(cc_job_init_matrix(*c, job, A.data(), 2 * m, m, input_occupation, n_samples, seed));
+    return run_job(*c, job, out_occupation, info);
 }
 BBFG_API_CATCH

@@ -19,6 +19,7 @@ struct CCSample {
     int k = 1;                    // next step (1-based); > n when finished
     std::vector<int32_t> pi;      // column order
     std::vector<int32_t> prefix;  // drawn output rows r_1 .. r_{k-1}
+    double tv = 0.0;              // sum over its steps of the draw-distribution error estimates
 };
 
 struct CCJob {
@@ -38,6 +39,10 @@ struct CCJob {
     std::vector<int32_t> out;   // n_samples x m
     double kernel_ms = 0.0;
     uint64_t n_addends = 0;
+    // largest tv over the finished samples: an estimate of the total-variation
+    // distance between a sample's law as computed and the exact law (each step's
+    // estimate from the minors' error estimates, summed over the steps)
+    double tv_max = 0.0;
 };
 
 struct ActiveSample {
@@ -70,6 +75,20 @@ size_t cc_job_footprint(int m, int n, int n_samples, double loss);
 int cc_job_init(Context& c, CCJob& job, const double* U, bool U_on_device, int m, const int32_t* occ, int n_samples,
                 double loss, uint64_t seed, bool stage_pinned = false);
 
+// Non-uniform loss (Sec. 4): the 2m x n job matrix of photons entering the
+// input modes of the m x m lossy interferometer matrix T (host, row-major
+// complex): the input columns of the isometry [T; R], R the upper-triangular
+// Cholesky factor of I - T^H T.  Any B with B^H B = I - T^H T gives the same
+// law on the first m output modes; R is one.  Fails with BBFG_EINVAL when T
+// is not a contraction (a pivot of I - T^H T below -1e-10).
+int cc_lossy_job_matrix(const double* T, int m, const int32_t* occ, std::vector<double>& A);
+
+// As cc_job_init, with the job matrix built on the host (rows x n complex,
+// e.g. by cc_lossy_job_matrix): rows candidate output modes, the first m
+// reported.
+int cc_job_init_matrix(Context& c, CCJob& job, const double* A_host, int rows, int m, const int32_t* occ,
+                       int n_samples, uint64_t seed, bool stage_pinned = false);
+
 // Draws sample s's column order (Fisher-Yates with SplitMix64).
 void cc_start_sample(CCJob& job, int s);
 
@@ -84,6 +103,7 @@ void cc_start_sample(CCJob& job, int s);
 struct CCPending {
     std::vector<size_t> act_of_step;  // step i advances act[act_of_step[i]]
     size_t o_drawn = 0;               // offset of the draws in w.cc_hmeta
+    size_t o_tv = 0;                  // offset of the steps' error estimates in w.cc_hmeta
     bool has_items = false;           // a minors launch was queued (timed by w.ev0/ev1)
     bool queued = false;
 };

@@ -36,6 +36,7 @@ namespace {
 struct SJob {
     uint64_t id = 0;
     std::vector<double> U;  // host copy, m x m complex
+    std::vector<double> A;  // lossy-matrix jobs: the 2m x n job matrix (host), else empty
     int m = 0;
     std::vector<int32_t> occ;
     int n_samples = 0;
@@ -43,7 +44,9 @@ struct SJob {
     uint64_t seed = 0;
     size_t footprint = 0;
     Clock::time_point t_submit, t_done;
-    int state = 0;  // 0 queued, 1 active, 2 done, 3 failed
+    int state = 0;  // 0 queued, 1 active, 2 done, 3 failed, 4 cancelled
+    bool cancel = false;  // cancellation requested while active
+    double tv = 0.0;      // the finished job's largest per-sample error estimate
     int err_code = 0;
     std::string err;
     std::unique_ptr<CCJob> cc;
@@ -180,19 +183,27 @@ void bbfg_server::run()
             std::vector<std::shared_ptr<SJob>> keep;
             for (auto& j : active) {
                 const bool done = j->cc->n == 0 || j->cc->finished == j->n_samples;
-                if (!done) {
+                // a cancelled job leaves with its own half, whose step has just
+                // ended (no queued step reads its samples any more)
+                const bool cancelled = j->cancel && j->half == which;
+                if (!done && !cancelled) {
                     keep.push_back(j);
                     continue;
                 }
-                j->out = j->cc->out;
+                if (cancelled) {
+                    j->state = 4;
+                } else {
+                    j->out = j->cc->out;
+                    j->tv = j->cc->tv_max;
+                    j->state = 2;
+                    st.jobs_done++;
+                    st.samples_done += (uint64_t)j->n_samples;
+                }
                 spare.push_back(std::move(j->cc));
                 half_work[j->half] -= j->weight;
-                j->state = 2;
                 j->t_done = Clock::now();
                 used -= j->footprint;
                 --outstanding;
-                st.jobs_done++;
-                st.samples_done += (uint64_t)j->n_samples;
             }
             if (keep.size() != active.size()) cv_done.notify_all();
             active.swap(keep);
@@ -239,8 +250,12 @@ void bbfg_server::run()
                 } else {
                     j->cc = std::make_unique<CCJob>();
                 }
-                rc = cc_job_init(*ctx, *j->cc, j->U.data(), false, j->m, j->occ.data(), j->n_samples, j->loss,
-                                 j->seed, true);
+                if (!j->A.empty())
+                    rc = cc_job_init_matrix(*ctx, *j->cc, j->A.data(), 2 * j->m, j->m, j->occ.data(), j->n_samples,
+                                            j->seed, true);
+                else
+                    rc = cc_job_init(*ctx, *j->cc, j->U.data(), false, j->m, j->occ.data(), j->n_samples, j->loss,
+                                     j->seed, true);
                 if (rc != BBFG_OK) break;
                 for (int s = 0; s < j->n_samples; ++s) cc_start_sample(*j->cc, s);
                 // work ~ samples x the addends of the last (largest) steps
@@ -281,6 +296,50 @@ void bbfg_server::run()
     }
 }
 
+namespace {
+
+// Queues a job; with `lossy_matrix`, U is the m x m lossy interferometer
+// matrix T and the job matrix [T; R] is built (and T validated) here.
+int submit_job(bbfg_server* srv, const bbfg_c128* U, int32_t m, const int32_t* input_occupation, int32_t n_samples,
+               double loss, uint64_t seed, bool lossy_matrix, uint64_t* job_id)
+{
+    if (!srv || !job_id) return set_error(BBFG_EINVAL, "NULL argument");
+    BBFG_TRY(cc_validate(U, m, input_occupation, n_samples, lossy_matrix ? 0.5 : loss));
+    auto j = std::make_shared<SJob>();
+    j->m = m;
+    j->U.resize(2 * (size_t)m * (size_t)m);
+    if (is_device_ptr(U)) {
+        BBFG_HIP(hipMemcpy(j->U.data(), U, sizeof(double) * j->U.size(), hipMemcpyDeviceToHost));
+    } else {
+        std::memcpy(j->U.data(), U, sizeof(double) * j->U.size());
+    }
+    if (lossy_matrix) {
+        BBFG_TRY(cc_lossy_job_matrix(j->U.data(), m, input_occupation, j->A));
+        j->U.clear();
+    }
+    j->occ.assign(input_occupation, input_occupation + m);
+    int n = 0;
+    for (int i = 0; i < m; ++i) n += input_occupation[i];
+    j->n_samples = n_samples;
+    j->loss = lossy_matrix ? 0.0 : loss;
+    j->seed = seed;
+    j->footprint = cc_job_footprint(m, n, n_samples, lossy_matrix ? 0.5 : loss);
+    j->t_submit = Clock::now();
+    std::lock_guard<std::mutex> lk(srv->mu);
+    if (srv->init_error != BBFG_OK) return set_error(srv->init_error, "%s", srv->init_message.c_str());
+    j->id = srv->next_id++;
+    srv->jobs[j->id] = j;
+    srv->queue.push_back(j);
+    srv->outstanding++;
+    srv->st.jobs_submitted++;
+    if (srv->queue.size() > srv->st.max_queued) srv->st.max_queued = srv->queue.size();
+    *job_id = j->id;
+    srv->cv_work.notify_one();
+    return BBFG_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int bs_server_create(size_t hbm_budget_bytes, int32_t max_active_jobs, bbfg_server** srv)
@@ -310,39 +369,18 @@ BBFG_API_CATCH
 int bs_server_submit(bbfg_server* srv, const bbfg_c128* U, int32_t m, const int32_t* input_occupation,
                      int32_t n_samples, double loss, uint64_t seed, uint64_t* job_id)
 try {
-    if (!srv || !job_id) return set_error(BBFG_EINVAL, "NULL argument");
-    BBFG_TRY(cc_validate(U, m, input_occupation, n_samples, loss));
-    auto j = std::make_shared<SJob>();
-    j->m = m;
-    j->U.resize(2 * (size_t)m * (size_t)m);
-    if (is_device_ptr(U)) {
-        BBFG_HIP(hipMemcpy(j->U.data(), U, sizeof(double) * j->U.size(), hipMemcpyDeviceToHost));
-    } else {
-        std::memcpy(j->U.data(), U, sizeof(double) * j->U.size());
-    }
-    j->occ.assign(input_occupation, input_occupation + m);
-    int n = 0;
-    for (int i = 0; i < m; ++i) n += input_occupation[i];
-    j->n_samples = n_samples;
-    j->loss = loss;
-    j->seed = seed;
-    j->footprint = cc_job_footprint(m, n, n_samples, loss);
-    j->t_submit = Clock::now();
-    std::lock_guard<std::mutex> lk(srv->mu);
-    if (srv->init_error != BBFG_OK) return set_error(srv->init_error, "%s", srv->init_message.c_str());
-    j->id = srv->next_id++;
-    srv->jobs[j->id] = j;
-    srv->queue.push_back(j);
-    srv->outstanding++;
-    srv->st.jobs_submitted++;
-    if (srv->queue.size() > srv->st.max_queued) srv->st.max_queued = srv->queue.size();
-    *job_id = j->id;
-    srv->cv_work.notify_one();
-    return BBFG_OK;
+    return submit_job(srv, U, m, input_occupation, n_samples, loss, seed, false, job_id);
 }
 BBFG_API_CATCH
 
-int bs_server_poll(bbfg_server* srv, uint64_t job_id, int32_t* out_occupation, double* latency_s)
+int bs_server_submit_lossy(bbfg_server* srv, const bbfg_c128* T, int32_t m, const int32_t* input_occupation,
+                           int32_t n_samples, uint64_t seed, uint64_t* job_id)
+try {
+    return submit_job(srv, T, m, input_occupation, n_samples, 0.0, seed, true, job_id);
+}
+BBFG_API_CATCH
+
+int bs_server_poll(bbfg_server* srv, uint64_t job_id, int32_t* out_occupation, double* latency_s, double* err_est)
 try {
     if (!srv) return set_error(BBFG_EINVAL, "srv is NULL");
     std::lock_guard<std::mutex> lk(srv->mu);
@@ -354,10 +392,43 @@ try {
         srv->jobs.erase(it);
         return set_error(j->err_code ? j->err_code : BBFG_EDEVICE, "job failed: %s", j->err.c_str());
     }
+    if (j->state == 4) {
+        srv->jobs.erase(it);
+        return set_error(BBFG_ECANCELED, "job %llu was cancelled", (unsigned long long)job_id);
+    }
     if (j->n_samples > 0 && !out_occupation) return set_error(BBFG_EINVAL, "out_occupation is NULL");
     if (j->n_samples > 0) std::memcpy(out_occupation, j->out.data(), sizeof(int32_t) * j->out.size());
     if (latency_s) *latency_s = std::chrono::duration<double>(j->t_done - j->t_submit).count();
+    if (err_est) *err_est = j->tv;
     srv->jobs.erase(it);
+    return BBFG_OK;
+}
+BBFG_API_CATCH
+
+int bs_server_cancel(bbfg_server* srv, uint64_t job_id)
+try {
+    if (!srv) return set_error(BBFG_EINVAL, "srv is NULL");
+    std::lock_guard<std::mutex> lk(srv->mu);
+    auto it = srv->jobs.find(job_id);
+    if (it == srv->jobs.end()) return set_error(BBFG_ENOTFOUND, "unknown job %llu", (unsigned long long)job_id);
+    auto j = it->second;
+    if (j->state == 0) {
+        // still queued: it never reaches the device
+        auto q = std::find(srv->queue.begin(), srv->queue.end(), j);
+        if (q != srv->queue.end()) srv->queue.erase(q);
+        j->state = 4;
+        j->t_done = Clock::now();
+        --srv->outstanding;
+        srv->st.jobs_cancelled++;
+        srv->cv_done.notify_all();
+    } else if (j->state == 1) {
+        // active: the worker retires it at the end of its half's current step
+        if (!j->cancel) srv->st.jobs_cancelled++;
+        j->cancel = true;
+    } else {
+        // finished (or failed) and not polled yet: its result is dropped
+        srv->jobs.erase(it);
+    }
     return BBFG_OK;
 }
 BBFG_API_CATCH

@@ -28,10 +28,20 @@ BBFG_FN kptr<T> kconst(const T* p)
     return (kptr<T>)p;
 }
 BBFG_FN uint32_t uniform_u32(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+// *p += v for a lane's own LDS slot, as an atomic without return value
+// (ds_add_f64): the walk issues it and moves on, holding no register for a
+// load of the old value
+BBFG_FN void lds_add(double* p, double v)
+{
+    (void)__hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
 }  // namespace bbfg
 #else
 #define BBFG_FN inline
 #include "emu_ptr.hpp"
+namespace bbfg {
+inline void lds_add(double* p, double v) { *p += v; }
+}  // namespace bbfg
 #endif
 
 namespace bbfg {
@@ -294,8 +304,12 @@ BBFG_FN void walk_unit(const WalkArgs& A, const PermDesc& d, uint32_t u_local, u
 // The weight ws enters the first prefix product, so each target's update is
 // one complex multiply-accumulate of its prefix and suffix products: four
 // fused multiply-adds instead of a complex product and a weighted add.
-template <int K, int G, typename Real>
-BBFG_FN void minors_accumulate(const Real* re, const Real* im, double ws, double* accr, double* acci)
+// MAG: also mag[t * mag_step] += mag_w * (|Re x| + |Im x|) for target t's
+// addend x, between its modulus and sqrt(2) times it (mag is a lane's own LDS
+// slots on the device).
+template <int K, int G, typename Real, bool MAG = false>
+BBFG_FN void minors_accumulate(const Real* re, const Real* im, double ws, double* accr, double* acci,
+                               double* mag = nullptr, uint32_t mag_step = 1, double mag_w = 0.0)
 {
     constexpr int T = K - G;
     Real pr[G], pim[G];
@@ -316,10 +330,18 @@ BBFG_FN void minors_accumulate(const Real* re, const Real* im, double ws, double
         if (t == G - 1) {
             accr[t] = accr[t] + (double)pr[t];
             acci[t] = acci[t] + (double)pim[t];
+            if constexpr (MAG) lds_add(mag + t * mag_step, mag_w * (__builtin_fabs((double)pr[t]) + __builtin_fabs((double)pim[t])));
         } else {
             const double ar = (double)pr[t], ai = (double)pim[t], br = (double)sr, bi = (double)si;
             accr[t] = __builtin_fma(-ai, bi, __builtin_fma(ar, br, accr[t]));
             acci[t] = __builtin_fma(ai, br, __builtin_fma(ar, bi, acci[t]));
+            if constexpr (MAG) {
+                // the addend itself (prefix times suffix), so that nothing of it
+                // can be formed before the suffix exists
+                const double xr = __builtin_fma(ar, br, -(ai * bi));
+                const double xi = __builtin_fma(ar, bi, ai * br);
+                lds_add(mag + t * mag_step, mag_w * (__builtin_fabs(xr) + __builtin_fabs(xi)));
+            }
         }
         if (t > 0) {
             if (t == G - 1) {
@@ -340,9 +362,14 @@ BBFG_FN void minors_accumulate(const Real* re, const Real* im, double ws, double
 // of the permanents (size K - 1) that each drop one of the last G columns.
 // The walk over the rows is the one of walk_unit; the signed weight w * s is
 // an integer below 2^53 (a product of binomials), hence exact.
+// mag[t * mag_step] receives the lane's estimate of the sum of |addend| of
+// target t: the positions of the lane's range whose index is a multiple of
+// d.mag_stride, each counted d.mag_stride times (every position when the
+// stride is 1).  The caller provides the G slots (the kernel keeps them in
+// LDS, off the register file).
 template <int K, int G, typename Real>
 BBFG_FN void walk_minors_unit(const WalkArgs& A, const PermDesc& d, uint32_t u_local, uint32_t lane, double* out_r,
-                              double* out_i)
+                              double* out_i, double* mag, uint32_t mag_step)
 {
     const uint32_t upg = (uint32_t)d.units_per_group;
     const uint32_t g = u_local / upg;
@@ -358,11 +385,16 @@ BBFG_FN void walk_minors_unit(const WalkArgs& A, const PermDesc& d, uint32_t u_l
     kptr<TabEntry> tab = kconst(d.tab);
     kptr<Real> a2 = kconst(RowsOf<Real>::a2(A) + 2 * d.a2_off);
     const uint32_t Q = d.Q;
+    const uint32_t mstride = uniform_u32(d.mag_stride);
+    const double mag_w = (double)mstride;
+    // positions until the next sampled one (0: this one)
+    uint32_t mwait = uniform_u32((uint32_t)((mstride - lin % mstride) % mstride));
 
 #pragma unroll
     for (int t = 0; t < G; ++t) {
         out_r[t] = 0.0;
         out_i[t] = 0.0;
+        mag[t * mag_step] = 0.0;
     }
     Real re[K], im[K];
     while (lin < lin1) {
@@ -373,18 +405,39 @@ BBFG_FN void walk_minors_unit(const WalkArgs& A, const PermDesc& d, uint32_t u_l
         double w;
         seed<K, Real>(A, d, lane_idx, h, t0, re, im, w);
         if (!valid) w = 0.0;
-        for (uint32_t t = t0; t < t1; ++t) {
-            if (t > t0) {
-                const uint32_t rowi = uniform_u32(tab[t].row);
-                kptr<Real> row = a2 + 2 * (size_t)rowi * K;
+        uint32_t t = t0;
+        while (t < t1) {
+            // plain steps up to the next sampled position (one basic block per
+            // step, as without sampling), then the sampled step
+            const uint32_t run = (t1 - t < mwait) ? t1 - t : mwait;
+            const uint32_t tp = t + run;
+            for (; t < tp; ++t) {
+                if (t > t0) {
+                    const uint32_t rowi = uniform_u32(tab[t].row);
+                    kptr<Real> row = a2 + 2 * (size_t)rowi * K;
 #pragma unroll
-                for (int j = 0; j < K; ++j) {
-                    re[j] += row[2 * j];
-                    im[j] += row[2 * j + 1];
+                    for (int j = 0; j < K; ++j) {
+                        re[j] += row[2 * j];
+                        im[j] += row[2 * j + 1];
+                    }
                 }
+                minors_accumulate<K, G, Real>(re, im, w * tab[t].s, out_r, out_i);
             }
-            const double ws = w * tab[t].s;
-            minors_accumulate<K, G, Real>(re, im, ws, out_r, out_i);
+            mwait -= run;
+            if (t < t1) {
+                if (t > t0) {
+                    const uint32_t rowi = uniform_u32(tab[t].row);
+                    kptr<Real> row = a2 + 2 * (size_t)rowi * K;
+#pragma unroll
+                    for (int j = 0; j < K; ++j) {
+                        re[j] += row[2 * j];
+                        im[j] += row[2 * j + 1];
+                    }
+                }
+                minors_accumulate<K, G, Real, true>(re, im, w * tab[t].s, out_r, out_i, mag, mag_step, mag_w);
+                ++t;
+                mwait = mstride - 1;
+            }
         }
         lin += (uint64_t)(t1 - t0);
     }

@@ -40,9 +40,10 @@ def run(A, M, slots: int, f32: bool = False, l_batch: int = 0):
     return complex(float.fromhex(re_), float.fromhex(im_)), float.fromhex(err), float.fromhex(kappa), int(units)
 
 
-def run_minors(A, M, l_batch: int, slots: int = 1):
+def run_minors(A, M, l_batch: int, slots: int = 1, with_err: bool = False):
     """Emulated minors walk: [perm(A without column l, M) for each l], planned with
-    unit length l_batch, or (l_batch = 0) to fill `slots` wavefront slots."""
+    unit length l_batch, or (l_batch = 0) to fill `slots` wavefront slots.
+    with_err: also the per-minor (rel_err_est, kappa) arrays."""
     A = np.ascontiguousarray(np.asarray(A, dtype=np.complex128))
     r, n = A.shape
     lines = [f"{r} {n} {int(slots)} 0 {int(l_batch)} 1", " ".join(str(int(m)) for m in M)]
@@ -52,8 +53,11 @@ def run_minors(A, M, l_batch: int, slots: int = 1):
                        timeout=600)
     if p.returncode != 0:
         raise RuntimeError(f"walk_emu failed ({p.returncode}): {p.stderr[-2000:]}")
-    vals = p.stdout.split()
-    return np.array([complex(float.fromhex(vals[2 * i]), float.fromhex(vals[2 * i + 1])) for i in range(n)])
+    v = [float.fromhex(x) for x in p.stdout.split()]
+    vals = np.array([complex(v[4 * i], v[4 * i + 1]) for i in range(n)])
+    if with_err:
+        return vals, np.array(v[2::4]), np.array(v[3::4])
+    return vals
 
 
 def run_cols(A, M, N, slots: int, l_batch: int = 0):

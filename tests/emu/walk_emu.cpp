@@ -18,7 +18,8 @@
 //         library does, equal multiplicities e >= 2 use (prod_j c_j)^e over the
 //         distinct columns, other ones the column-expanded matrix.
 // stdout: re im rel_err_est kappa units   (hex floats, then an integer), or for
-//         minors n lines "re im" (permanent without column l, l = 0 .. n-1)
+//         minors n lines "re im rel_err_est kappa" (permanent without column l,
+//         l = 0 .. n-1)
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -247,11 +248,11 @@ void butterfly(ddv* sr, ddv* si)
 }
 
 template <int KMIN, int KMAX>
-void run_minor_unit(const WalkArgs& W, const PermDesc& d, uint32_t u, uint32_t lane, double* r, double* i)
+void run_minor_unit(const WalkArgs& W, const PermDesc& d, uint32_t u, uint32_t lane, double* r, double* i, double* mag)
 {
     if constexpr (KMIN <= KMAX) {
-        if (d.n == KMIN) walk_minors_unit<KMIN, minor_group(KMIN), double>(W, d, u, lane, r, i);
-        else run_minor_unit<KMIN + 1, KMAX>(W, d, u, lane, r, i);
+        if (d.n == KMIN) walk_minors_unit<KMIN, minor_group(KMIN), double>(W, d, u, lane, r, i, mag, 1);
+        else run_minor_unit<KMIN + 1, KMAX>(W, d, u, lane, r, i, mag);
     }
 }
 
@@ -270,9 +271,9 @@ int emulate_minors(int n_rows, int K, long long slots, long long l_batch, const 
         std::fprintf(stderr, "plan error %d: %s\n", rc, err.c_str());
         return 2;
     }
-    std::vector<double> out(2 * (size_t)K, 0.0);
+    std::vector<double> out(4 * (size_t)K, 0.0);
     if (K == 1) {
-        std::printf("%a %a\n", 1.0, 0.0);
+        std::printf("%a %a %a %a\n", 1.0, 0.0, 0.0, 1.0);
         return 0;
     }
     const int r = P.r;
@@ -321,7 +322,9 @@ int emulate_minors(int n_rows, int K, long long slots, long long l_batch, const 
         d.lane_product = P.lane_product;
         d.groups = P.groups;
         d.scale = std::ldexp(1.0, 1 - (K - 1));
+        d.err_coeff = P.err_coeff * 0x1.0p-53;
         d.targets = (uint32_t)G;
+        d.mag_stride = P.n_addends > kMagExactAddends ? kMagStride : 1u;
         WalkArgs W;
         std::memset(&W, 0, sizeof W);
         W.rowinfo = P.rows.data();
@@ -333,52 +336,73 @@ int emulate_minors(int n_rows, int K, long long slots, long long l_batch, const 
         emu_register(P.table->data(), sizeof(TabEntry) * P.table->size());
         emu_register(binom.data(), sizeof(double) * binom.size());
         emu_register(arena.data(), sizeof(double) * arena.size());
-        // partial (unit, target) -> (re hi, re lo, im hi, im lo)
-        std::vector<double> part((size_t)P.units * G * 4);
+        // partial (unit, target) -> (re hi, re lo, im hi, im lo, magnitude sum)
+        std::vector<double> part((size_t)P.units * G * kPartialDoubles);
         for (uint64_t u = 0; u < P.units; ++u) {
-            std::vector<double> lr((size_t)kWave * G), li((size_t)kWave * G);
+            std::vector<double> lr((size_t)kWave * G), li((size_t)kWave * G), lm((size_t)kWave * G);
             for (uint32_t lane = 0; lane < (uint32_t)kWave; ++lane)
                 run_minor_unit<2, kMaxN>(W, d, (uint32_t)u, lane, lr.data() + (size_t)lane * G,
-                                         li.data() + (size_t)lane * G);
+                                         li.data() + (size_t)lane * G, lm.data() + (size_t)lane * G);
             for (int t = 0; t < G; ++t) {
                 ddv sr[kWave], si[kWave];
+                double sa[kWave];
                 for (int l = 0; l < kWave; ++l) {
                     sr[l] = {lr[(size_t)l * G + t], 0.0};
                     si[l] = {li[(size_t)l * G + t], 0.0};
+                    sa[l] = lm[(size_t)l * G + t];
                 }
                 butterfly(sr, si);
-                double* p = part.data() + ((size_t)u * G + t) * 4;
+                for (int off = 1; off < kWave; off <<= 1) {
+                    double na[kWave];
+                    for (int l = 0; l < kWave; ++l) na[l] = sa[l] + sa[l ^ off];
+                    for (int l = 0; l < kWave; ++l) sa[l] = na[l];
+                }
+                double* p = part.data() + ((size_t)u * G + t) * kPartialDoubles;
                 p[0] = sr[0].hi;
                 p[1] = sr[0].lo;
                 p[2] = si[0].hi;
                 p[3] = si[0].lo;
+                p[4] = sa[0];
             }
         }
         constexpr int T = 256;
         for (int t = 0; t < G; ++t) {
             if (t0 + t < gi * G) continue;  // owned by the previous group
             std::vector<ddv> shr(T), shi(T);
+            std::vector<double> sha(T);
             for (int th = 0; th < T; ++th) {
                 ddv a = {0.0, 0.0}, b = {0.0, 0.0};
+                double c = 0.0;
                 for (uint64_t u = (uint64_t)th; u < P.units; u += T) {
-                    const double* p = part.data() + ((size_t)u * G + t) * 4;
+                    const double* p = part.data() + ((size_t)u * G + t) * kPartialDoubles;
                     a = dd_add(a, {p[0], p[1]});
                     b = dd_add(b, {p[2], p[3]});
+                    c += p[4];
                 }
                 shr[(size_t)th] = a;
                 shi[(size_t)th] = b;
+                sha[(size_t)th] = c;
             }
             for (int sst = T / 2; sst > 0; sst >>= 1)
                 for (int th = 0; th < sst; ++th) {
                     shr[(size_t)th] = dd_add(shr[(size_t)th], shr[(size_t)(th + sst)]);
                     shi[(size_t)th] = dd_add(shi[(size_t)th], shi[(size_t)(th + sst)]);
+                    sha[(size_t)th] = sha[(size_t)th] + sha[(size_t)(th + sst)];
                 }
             const int l = t0 + t;
-            out[2 * (size_t)l] = (shr[0].hi + shr[0].lo) * d.scale;
-            out[2 * (size_t)l + 1] = (shi[0].hi + shi[0].lo) * d.scale;
+            const double re = (shr[0].hi + shr[0].lo) * d.scale;
+            const double im = (shi[0].hi + shi[0].lo) * d.scale;
+            const double mag = std::sqrt(re * re + im * im);
+            const double kappa = mag > 0.0 ? sha[0] * d.scale / mag : INFINITY;
+            out[4 * (size_t)l] = re;
+            out[4 * (size_t)l + 1] = im;
+            out[4 * (size_t)l + 2] = kappa * d.err_coeff;
+            out[4 * (size_t)l + 3] = kappa;
         }
     }
-    for (int l = 0; l < K; ++l) std::printf("%a %a\n", out[2 * (size_t)l], out[2 * (size_t)l + 1]);
+    for (int l = 0; l < K; ++l)
+        std::printf("%a %a %a %a\n", out[4 * (size_t)l], out[4 * (size_t)l + 1], out[4 * (size_t)l + 2],
+                    out[4 * (size_t)l + 3]);
     return 0;
 }
 

@@ -13,6 +13,10 @@ from paper_2309_07027_amd import inputs as I
 from tests.emu import emu
 
 TOL = 1e-10
+# Sums with a conditioning kappa (sum |addend| / |perm|) above this are held to
+# their own reported error estimate instead of TOL (the FP64 walk's error grows
+# like kappa * u; the estimate is kappa * u * (n + sqrt(Q))).
+KAPPA_WELL = 1e6
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -95,18 +99,43 @@ def test_minors_walk_matches_oracle(oracle, modes, Ks):
     against the oracle's generalized permanent of the matrix without that column;
     K spans one group (small K) and several groups, with a padded last group
     (K = 21, 31, 40).  Heavy bunching (5 modes) keeps the large-K sums short but
-    makes them ill-conditioned (kappa up to ~1e7 at K = 40): the bar is 1e-10 or
-    the first-order bound kappa * (K + 64) * u, whichever is larger, with kappa
-    the oracle's sum of |addend| over |perm|."""
+    makes them ill-conditioned (kappa up to ~3e7 at K = 40).  The bar (the
+    reading of the relative-error target for ill-conditioned sums): 1e-10 where
+    the oracle's kappa is at most KAPPA_WELL, and otherwise the walk's own
+    estimate; the error never exceeds that estimate in any case."""
     rng = np.random.default_rng(77 + modes)
     for K in Ks:
         A, M = _minor_case(rng, K, modes)
         refs = [oracle.perm_generalized(np.delete(A, l, axis=1), M, with_abs=True) for l in range(K)]
         for L, slots in ((64, 1), (512, 1), (0, 2048)):
-            got = emu.run_minors(A, M, L, slots)
+            got, est, kap = emu.run_minors(A, M, L, slots, with_err=True)
             for l, (ref, absum) in enumerate(refs):
-                bar = max(TOL, absum / abs(ref) * (K + 64) * 2.0 ** -53)
-                assert rel(got[l], ref) <= bar, (K, l, M, L)
+                e = rel(got[l], ref)
+                assert e <= est[l], (K, l, M, L, e, est[l])
+                if absum / abs(ref) <= KAPPA_WELL:
+                    assert e <= TOL, (K, l, M, L, e)
+
+
+@pytest.mark.parametrize("K,M", [(14, [1] * 13), (24, [2] * 6 + [1] * 11), (36, [4] * 8 + [3])])
+def test_minors_kappa_estimate(oracle, K, M):
+    """The walk's per-minor conditioning (magnitudes |re| + |im| of the addends,
+    taken at every Gray position up to 2^20 addends and at every 257th beyond)
+    against the oracle's sum of |addend| / |perm|.  Every position: between 1
+    and sqrt(2) times it (the 1-norm bound), up to rounding.  Sampled (K = 36
+    has C' = 3 * 5^8 > 2^20 addends): an estimate from ~4500 positions of a
+    heavy-tailed sum, within a factor of about 2 either way."""
+    U = I.haar_unitary(300 + K)
+    A = np.ascontiguousarray(U[:len(M)][:, :K])
+    Mp = list(M)
+    Mp[int(np.argmin(M))] -= 1
+    sampled = np.prod([m + 1 for m in Mp]) > 2 ** 20
+    got, est, kap = emu.run_minors(A, M, 512, 1, with_err=True)
+    for l in range(K):
+        ref, absum = oracle.perm_generalized(np.delete(A, l, axis=1), M, with_abs=True)
+        ratio = kap[l] / (absum / abs(ref))
+        lo, hi = (0.4, 2.5) if sampled else (1.0 - 1e-12, np.sqrt(2.0) + 1e-12)
+        assert lo <= ratio <= hi, (K, l, ratio)
+        assert rel(got[l], ref) <= min(TOL, est[l]), (K, l)
 
 
 @pytest.mark.parametrize("seed", [31, 32])

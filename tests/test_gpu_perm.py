@@ -4,6 +4,7 @@ the double-double CPU oracle, through the C ABI.
 Tolerance: relative error <= 1e-10 (Eq. relative_error of Sec. 3.2) for the
 FP64 path, on every case.  The FP32 path reports its error against the oracle.
 """
+import hashlib
 import json
 import math
 import os
@@ -18,7 +19,11 @@ from paper_2309_07027_amd import inputs as I
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-10
-GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "perm_golden.json")
+# Leave-one-column-out sums with a conditioning kappa (sum |addend| / |perm|)
+# above this are held to their own reported error estimate instead of TOL.
+KAPPA_WELL = 1e6
+GOLDEN_DIR = os.path.join(os.path.dirname(__file__), "golden")
+GOLDEN = os.path.join(GOLDEN_DIR, "perm_golden.json")
 
 
 def say(*a):
@@ -223,29 +228,53 @@ def test_autotune_roundtrip(tmp_path):
         assert rel(g, B.perm_bbfg(A, M)) <= TOL
 
 
-def test_c3_full_batch(golden):
+def _input_hash(A, M):
+    # the hash tests/golden/make_golden.py stores next to each batch item
+    h = hashlib.sha256()
+    h.update(np.ascontiguousarray(A, dtype=np.complex128).tobytes())
+    h.update(np.ascontiguousarray(M, dtype=np.int32).tobytes())
+    return h.hexdigest()[:16]
+
+
+def _c3_golden():
+    vals, hashes, absums = {}, {}, {}
+    with open(os.path.join(GOLDEN_DIR, "c3_all.txt")) as fh:
+        for line in fh:
+            if line.startswith("#"):
+                continue
+            i, n, r, h, re_, im_, ab = line.split()
+            vals[int(i)] = complex(float(re_), float(im_))
+            hashes[int(i)] = h
+            absums[int(i)] = float(ab)
+    return vals, hashes, absums
+
+
+def test_c3_full_batch():
+    """All 4096 items of the uneven batch against the oracle values stored by
+    tests/golden/make_golden.py (each with a hash of its input bytes, so a host
+    whose LAPACK regenerated an input differently is caught): FP64 within TOL
+    and within its estimate on every item; the FP32 path's error against the
+    oracle reported (median, p99, max) and covered by its estimate on every
+    item."""
     items = I.c3(4096)
-    idx = [int(k.split("_")[1]) for k in golden if k.startswith("c3_")]
-    for i in idx:
-        A, M, _, _ = golden[f"c3_{i}"]
-        items[i] = (A, M)
+    vals, hashes, absums = _c3_golden()
+    bad = [i for i, (A, M) in enumerate(items) if _input_hash(A, M) != hashes[i]]
+    assert not bad, f"{len(bad)} regenerated inputs differ from the stored oracle inputs (first {bad[:5]})"
+    ref = np.array([vals[i] for i in range(4096)])
     say("case c3 4096 items fp64")
     out, err = B.perm_batch(items, with_err=True)
-    assert np.isfinite(out).all()
-    for i in idx:
-        assert rel(out[i], golden[f"c3_{i}"][2]) <= TOL, i
-        assert rel(out[i], golden[f"c3_{i}"][2]) <= err[i]
-    say(f"  fp64 error estimates: median {np.median(err):.2e} max {err.max():.2e}")
-    assert (err < 1e-8).all()
-    # FP32 path: error against the FP64 result, reported per item
+    e64 = np.abs(out - ref) / np.abs(ref)
+    say(f"  fp64 rel err vs oracle: median {np.median(e64):.2e} max {e64.max():.2e}; "
+        f"estimate median {np.median(err):.2e} max {err.max():.2e}")
+    assert (e64 <= TOL).all(), np.nonzero(e64 > TOL)[0][:10]
+    assert (e64 <= err).all(), np.nonzero(e64 > err)[0][:10]
     say("case c3 4096 items fp32")
     out32, err32 = B.perm_batch(items, precision=B.BBFG_FP32, with_err=True)
-    e = np.abs(out32 - out) / np.abs(out)
-    say(f"  fp32 rel err: median {np.median(e):.2e} max {e.max():.2e}; estimate median {np.median(err32):.2e}")
-    assert np.median(e) < 1e-4
-    for i in idx:
-        ref = golden[f"c3_{i}"][2]
-        assert rel(out32[i], ref) < 1e-2
+    e32 = np.abs(out32 - ref) / np.abs(ref)
+    say(f"  fp32 rel err vs oracle: median {np.median(e32):.2e} p99 {np.percentile(e32, 99):.2e} "
+        f"max {e32.max():.2e}; estimate covers {np.mean(e32 <= err32) * 100:.1f} %")
+    assert np.median(e32) < 1e-4
+    assert (e32 <= err32).all(), np.nonzero(e32 > err32)[0][:10]
 
 
 def test_device_pointers():
@@ -302,17 +331,45 @@ def test_minors_vs_oracle(oracle):
     """perm_minors (one joint leave-one-column-out walk) against the oracle's
     generalized permanent of every column-deleted matrix: K = 2..24 over 60
     modes (one and two target groups) and K up to 44 with heavy bunching (one
-    group up to 36 columns, two groups at 37 and 44)."""
+    group up to 36 columns, two groups at 37 and 44).  Every minor is within its
+    reported error estimate; those with the oracle's conditioning kappa <=
+    KAPPA_WELL within TOL (the heavily bunched K = 36 .. 44 cases reach kappa
+    ~1e7, where the FP64 walk's error can pass 1e-10)."""
     rng = np.random.default_rng(303)
     cases = [(K, 60) for K in (2, 3, 4, 7, 12, 16, 20, 24)] + [(K, 5) for K in (28, 33, 36, 37)] + [(44, 4)]
     for K, modes in cases:
         A, M = _minor_case(rng, K, modes)
         say(f"case minors K={K} M={M.tolist()}")
-        got = B.perm_minors(A, M)
+        got, est = B.perm_minors(A, M, with_err=True)
         for l in range(K):
             ref, absum = oracle.perm_generalized(np.delete(A, l, axis=1), M, with_abs=True)
-            bar = max(TOL, absum / abs(ref) * (K + 64) * 2.0 ** -53)
-            assert rel(got[l], ref) <= bar, (K, l, M.tolist())
+            e = rel(got[l], ref)
+            assert e <= est[l], (K, l, M.tolist(), e, est[l])
+            if absum / abs(ref) <= KAPPA_WELL:
+                assert e <= TOL, (K, l, M.tolist(), e)
+
+
+def _golden_minors():
+    with open(os.path.join(GOLDEN_DIR, "minors_golden.json")) as fh:
+        return json.load(fh)["cases"]
+
+
+@pytest.mark.parametrize("name", ["k30_distinct", "k32_bunched", "k36_bunched", "k37_bunched", "k40_bunched"])
+def test_minors_golden(name):
+    """Stored oracle values (tests/golden/minors_golden.json): the 30 minors of
+    a 30-column step with 29 distinct rows (2^28 addends each, the 25-30-column
+    kernel), and bunched 32-40-column steps (kappa 3e4 .. 9e5, the 31-32- and
+    33-48-column kernels).  Every minor within TOL and within its estimate."""
+    case = next(c for c in _golden_minors() if c["name"] == name)
+    K = case["K"]
+    A = np.array([complex(x, y) for x, y in case["A"]]).reshape(len(case["M"]), K)
+    M = np.asarray(case["M"], dtype=np.int32)
+    say(f"case minors golden {name} K={K}")
+    got, est = B.perm_minors(A, M, with_err=True)
+    for l, v in enumerate(case["minors"]):
+        ref = complex(v[0] + v[1], v[2] + v[3])
+        e = rel(got[l], ref)
+        assert e <= TOL and e <= est[l], (name, l, e, est[l])
 
 
 def test_minors_match_emulation_bitwise():
@@ -416,6 +473,36 @@ def test_column_multiplicities_vs_oracle_and_expansion(oracle):
             assert v == e, (n, v, e)
 
 
+@pytest.mark.parametrize("name", ["e2_c17", "e2_c20", "e2_c22", "e2_c24", "mixed_n24", "mixed_n28", "mixed_n32"])
+def test_column_multiplicities_golden(name):
+    """Stored oracle values of the column-expanded matrix
+    (tests/golden/cols_golden.json): equal multiplicity 2 on 17 .. 24 distinct
+    columns (n = 34 .. 48, the column-power kernel's 24-column bucket) and mixed
+    multiplicities at n = 24 .. 32.  Within TOL where the oracle's kappa is at
+    most KAPPA_WELL, and always within the reported estimate; the equal-
+    multiplicity cases also bitwise against the CPU emulation of that kernel's
+    split."""
+    with open(os.path.join(GOLDEN_DIR, "cols_golden.json")) as fh:
+        case = next(c for c in json.load(fh)["cases"] if c["name"] == name)
+    M = np.asarray(case["M"], dtype=np.int32)
+    N = np.asarray(case["N"], dtype=np.int32)
+    A = np.array([complex(x, y) for x, y in case["A"]]).reshape(len(M), len(N))
+    ref = complex(case["re"][0] + case["re"][1], case["im"][0] + case["im"][1])
+    kappa = case["abs_sum"] / abs(ref)
+    say(f"case cols golden {name} n={int(N.sum())} distinct={len(N)} kappa={kappa:.1e}")
+    v, info = B.perm_bbfg_cols(A, M, N, with_info=True)
+    e = rel(v, ref)
+    assert e <= info["rel_err_est"], (name, e, info["rel_err_est"])
+    if kappa <= KAPPA_WELL:
+        assert e <= TOL, (name, e)
+    if name.startswith("e2"):
+        from tests.emu import emu
+        emu.build()
+        waves, ncu = B.walk_occupancy(len(N), B.BBFG_COLS)
+        ev, *_ = emu.run_cols(A, M, N, waves * ncu)
+        assert v == ev, (name, v, ev)
+
+
 def test_column_multiplicities_edges():
     A = np.ones((2, 3), dtype=np.complex128)
     assert B.perm_bbfg_cols(A, [2, 1], [1, 1, 1]) == pytest.approx(6)      # perm(J_3)
@@ -449,20 +536,20 @@ def test_batch_ragged_and_empty_items(oracle):
     assert abs(out[7] - ref48) / ref48 <= max(TOL, err[7])
 
 
-def test_c3_batch_after_autotuning_vs_golden(golden):
+def test_c3_batch_after_autotuning_vs_golden():
     """The 4096-item batch as bench.py times it: unit lengths tuned on this
-    device first, then FP64 and FP32 against the oracle's sampled items."""
+    device first, then every FP64 item against the stored oracle values (the
+    split changed, so the rounding did) and FP32 within its estimates."""
     B.autotune(8, 24)
     B.autotune(8, 24, precision=B.BBFG_FP32)
     items = I.c3(4096)
-    idx = [int(k.split("_")[1]) for k in golden if k.startswith("c3_")]
-    for i in idx:
-        A, M, _, _ = golden[f"c3_{i}"]
-        items[i] = (A, M)
+    vals, hashes, _ = _c3_golden()
+    ref = np.array([vals[i] for i in range(4096)])
     say("case c3 4096 items after autotuning")
     out = B.perm_batch(items)
-    out32 = B.perm_batch(items, precision=B.BBFG_FP32)
-    for i in idx:
-        ref = golden[f"c3_{i}"][2]
-        assert rel(out[i], ref) <= TOL, i
-        assert rel(out32[i], ref) < 1e-2, i
+    out32, err32 = B.perm_batch(items, precision=B.BBFG_FP32, with_err=True)
+    e64 = np.abs(out - ref) / np.abs(ref)
+    e32 = np.abs(out32 - ref) / np.abs(ref)
+    say(f"  fp64 max {e64.max():.2e}; fp32 median {np.median(e32):.2e} max {e32.max():.2e}")
+    assert (e64 <= TOL).all(), np.nonzero(e64 > TOL)[0][:10]
+    assert (e32 <= err32).all(), np.nonzero(e32 > err32)[0][:10]

@@ -78,6 +78,13 @@ def test_validation_errors():
     with pytest.raises(B.BBFGError) as e:
         B.bs_sample(np.eye(60, dtype=complex), occ, 1)
     assert e.value.code == B.BBFG_ERANGE
+    # the lossy interferometer matrix must be a contraction (checked on the host)
+    with pytest.raises(B.BBFGError) as e:
+        B.bs_sample_lossy(1.01 * U, [1, 1, 0, 0], 2)
+    assert e.value.code == B.BBFG_EINVAL and "contraction" in str(e.value)
+    with pytest.raises(B.BBFGError) as e:
+        B.bs_sample_lossy(np.eye(129, dtype=complex), [1] + [0] * 128, 1)
+    assert e.value.code == B.BBFG_ERANGE
 
 
 def test_empty_permanent_is_one_without_device():
