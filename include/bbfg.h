@@ -133,6 +133,27 @@ int perm_bbfg(const bbfg_c128 *A, int32_t n_rows, const int32_t *row_mult, int32
               bbfg_c128 *out, bbfg_info *info);
 
 /*
+ * perm_bbfg_noalloc -- perm_bbfg for callers that cannot allocate device
+ * memory (tight serving loops, code that must not call hipMalloc).  Same
+ * arguments, plan, kernels and result bits as perm_bbfg; every device buffer
+ * it uses (binomial table, metadata, Gray table, staged host A, gathered rows,
+ * unit partials, results) lives in one file-scope device array of 2 MiB per
+ * device, which stays allocated until the process ends.  It calls no
+ * hipMalloc/hipFree or other device-allocating routine (host planning uses
+ * ordinary heap memory).  bbfg_init takes the array's address on the current
+ * device; a first call on a device without it does so itself.
+ *
+ * Limits: n_cols <= BBFG_MAX_N (else BBFG_ERANGE); a host A has at most 256
+ * rows (BBFG_ERANGE beyond); the walk is split into at most 32768 units
+ * (longer units for the largest sums).  info->kernel_ms is not measured (0).
+ * Calls are serialised inside the process (they share the array); the call is
+ * synchronous, so nothing of it overlaps the next call.
+ * Errors: as perm_bbfg.
+ */
+int perm_bbfg_noalloc(const bbfg_c128 *A, int32_t n_rows, const int32_t *row_mult, int32_t n_cols,
+                      bbfg_c128 *out, bbfg_info *info);
+
+/*
  * perm_batch -- many generalized permanents of uneven sizes in one persistent
  * launch (the batched evaluation of App. A.4, generalised to unequal shapes and
  * multiplicities).

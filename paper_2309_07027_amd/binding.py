@@ -81,6 +81,7 @@ SIGNATURES = {
     "bbfg_set_stream": (ctypes.c_int, [_P]),
     "bbfg_set_cache_limits": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_uint64]),
     "perm_bbfg": (ctypes.c_int, [_P, _I32, _PI32, _I32, _P, ctypes.POINTER(Info)]),
+    "perm_bbfg_noalloc": (ctypes.c_int, [_P, _I32, _PI32, _I32, _P, ctypes.POINTER(Info)]),
     "perm_batch": (ctypes.c_int, [_I32, _P, _PI64, _PI32, _PI32, _PI64, _PI32, _I32, _P, _PD]),
     "perm_minors": (ctypes.c_int, [_P, _I32, _PI32, _I32, _P, _PD]),
     "perm_bbfg_cols": (ctypes.c_int, [_P, _I32, _PI32, _I32, _PI32, _P, ctypes.POINTER(Info)]),
@@ -197,6 +198,18 @@ def perm_bbfg(A, row_mult=None, with_info: bool = False):
     out = np.zeros(1, dtype=np.complex128)
     info = Info()
     _check(lib().perm_bbfg(ptr, r, mp, n, ctypes.c_void_p(out.ctypes.data), ctypes.byref(info)))
+    del keep
+    return (complex(out[0]), info.as_dict()) if with_info else complex(out[0])
+
+
+def perm_bbfg_noalloc(A, row_mult=None, with_info: bool = False):
+    """perm_bbfg through the entry point that allocates no device memory."""
+    ptr, keep, shape = _cmat_ptr(A)
+    r, n = shape
+    mult, mp = _i32(np.ones(r, dtype=np.int32) if row_mult is None else row_mult)
+    out = np.zeros(1, dtype=np.complex128)
+    info = Info()
+    _check(lib().perm_bbfg_noalloc(ptr, r, mp, n, ctypes.c_void_p(out.ctypes.data), ctypes.byref(info)))
     del keep
     return (complex(out[0]), info.as_dict()) if with_info else complex(out[0])
 

@@ -11,23 +11,6 @@ using namespace bbfg;
 
 namespace {
 
-// Host-side validation of one matrix shape (before any device work).
-int validate_shape(const int32_t* mult, int32_t n_rows, int32_t n_cols, int max_n)
-{
-    if (n_rows < 0) return set_error(BBFG_EINVAL, "n_rows = %d < 0", n_rows);
-    if (n_cols < 0) return set_error(BBFG_EINVAL, "n_cols = %d < 0", n_cols);
-    if (n_cols > max_n) return set_error(BBFG_ERANGE, "n_cols = %d exceeds the maximum %d", n_cols, max_n);
-    if (n_rows > 0 && !mult) return set_error(BBFG_EINVAL, "row_mult is NULL");
-    int64_t sum = 0;
-    for (int32_t i = 0; i < n_rows; ++i) {
-        if (mult[i] < 0) return set_error(BBFG_EINVAL, "row_mult[%d] = %d < 0", i, mult[i]);
-        sum += mult[i];
-    }
-    if (sum != n_cols)
-        return set_error(BBFG_EINVAL, "sum(row_mult) = %lld differs from n_cols = %d", (long long)sum, n_cols);
-    return BBFG_OK;
-}
-
 int write_results(void* out, const double* vals, size_t count)
 {
     if (is_device_ptr(out)) {
@@ -70,7 +53,8 @@ int bbfg_version(void) { return BBFG_VERSION; }
 int bbfg_init(void)
 try {
     Context* c = nullptr;
-    return get_context(&c);
+    BBFG_TRY(get_context(&c));
+    return noalloc_setup();
 }
 BBFG_API_CATCH
 

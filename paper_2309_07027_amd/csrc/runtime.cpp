@@ -35,6 +35,22 @@ int set_error(int code, const char* fmt, ...)
 
 const char* last_error() { return t_err.c_str(); }
 
+int validate_shape(const int32_t* mult, int32_t n_rows, int32_t n_cols, int max_n)
+{
+    if (n_rows < 0) return set_error(BBFG_EINVAL, "n_rows = %d < 0", n_rows);
+    if (n_cols < 0) return set_error(BBFG_EINVAL, "n_cols = %d < 0", n_cols);
+    if (n_cols > max_n) return set_error(BBFG_ERANGE, "n_cols = %d exceeds the maximum %d", n_cols, max_n);
+    if (n_rows > 0 && !mult) return set_error(BBFG_EINVAL, "row_mult is NULL");
+    int64_t sum = 0;
+    for (int32_t i = 0; i < n_rows; ++i) {
+        if (mult[i] < 0) return set_error(BBFG_EINVAL, "row_mult[%d] = %d < 0", i, mult[i]);
+        sum += mult[i];
+    }
+    if (sum != n_cols)
+        return set_error(BBFG_EINVAL, "sum(row_mult) = %lld differs from n_cols = %d", (long long)sum, n_cols);
+    return BBFG_OK;
+}
+
 hipStream_t current_stream() { return t_stream; }
 void set_current_stream(hipStream_t s) { t_stream = s; }
 

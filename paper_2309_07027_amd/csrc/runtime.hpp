@@ -26,6 +26,8 @@ namespace bbfg {
 // ---- errors (thread-local message) ----------------------------------------
 int set_error(int code, const char* fmt, ...);
 const char* last_error();
+// Host-side validation of one matrix shape (before any device work).
+int validate_shape(const int32_t* mult, int32_t n_rows, int32_t n_cols, int max_n);
 
 #define BBFG_HIP(expr)                                                                              \
     do {                                                                                            \
@@ -164,6 +166,9 @@ enum PlanMode { PLAN_SINGLE = 0, PLAN_BATCH = 1 };
 
 // Context of the current HIP device (created on first use).
 int get_context(Context** out);
+// Device address of the no-allocation entry point's scratch array on the
+// current device, taken once per device (noalloc.hip).
+int noalloc_setup();
 hipStream_t current_stream();
 void set_current_stream(hipStream_t s);
 
