@@ -107,10 +107,17 @@ def cpu_baseline(sample_terms: int):
         O.set_threads(threads)
     model = ""
     try:
-        with open("/proc/cpuinfo") as fh:
-            model = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), "")
-    except OSError:
+        import subprocess
+        lines = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout.splitlines()
+        model = next((l.split(":", 1)[1].strip() for l in lines if l.startswith("Model name")), "")
+    except (OSError, subprocess.SubprocessError):
         pass
+    if not model:
+        try:
+            with open("/proc/cpuinfo") as fh:
+                model = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), "")
+        except OSError:
+            pass
     return {"value": round(gflops, 4), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
             "sample": f"case (a) n=30: addends [0, {sample_terms}) of 2^29 (Gray-coded Eq. bbfg in "
                       f"double-double), {dt:.2f} s; GFLOP/s at the same 8n-4 flops per addend",
@@ -119,8 +126,29 @@ def cpu_baseline(sample_terms: int):
             "cpu_model": model}
 
 
+def stored_oracle_c3(np):
+    """The oracle's values of the 4096 batch items (tests/golden/c3_all.txt, written
+    by tests/golden/make_golden.py from the double-double oracle), or None."""
+    try:
+        vals = {}
+        with open(os.path.join(ROOT, "tests", "golden", "c3_all.txt")) as fh:
+            for line in fh:
+                if not line.startswith("#"):
+                    f = line.split()
+                    vals[int(f[0])] = complex(float(f[4]), float(f[5]))
+        return np.array([vals[i] for i in range(4096)])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def err_stats(np, e):
+    return {"median": float(f"{np.median(e):.3g}"), "p99": float(f"{np.percentile(e, 99):.3g}"),
+            "max": float(f"{e.max():.3g}")}
+
+
 def batch_section(B, I, torch, np, reps: int):
-    """4096 uneven permanents in one launch: FP64 and FP32 (device-resident input)."""
+    """4096 uneven permanents in one launch: FP64 and FP32 (device-resident input),
+    and the Ryser formula on the same walk; errors against the stored oracle values."""
     items = I.c3(4096)
     Ap, ao, nr, Mp, mo, nc = B.pack_batch(items)
     Ad = torch.from_numpy(Ap).to("cuda")
@@ -128,7 +156,7 @@ def batch_section(B, I, torch, np, reps: int):
     fl = sum(flops(A.shape[1], M, cprime_of(M)) for A, M in items)
     out = {"items": len(items), "n_range": [8, 24], "n_addends": addends, "flops": fl}
     vals = {}
-    for prec, name in ((B.BBFG_FP64, "fp64"), (B.BBFG_FP32, "fp32")):
+    for prec, name in ((B.BBFG_FP64, "fp64"), (B.BBFG_FP32, "fp32"), (B.BBFG_RYSER, "ryser_fp64")):
         for _ in range(3):  # plans, tables, graph capture
             B.perm_batch_packed(Ad, ao, nr, Mp, mo, nc, precision=prec)
         walls, dev, graph = [], [], []
@@ -148,15 +176,53 @@ def batch_section(B, I, torch, np, reps: int):
                      "pct_fp64_peak_wall": round(100 * fl / w / 1e12 / FP64_PEAK_TFLOPS, 2)}
     v64, e64 = vals["fp64"]
     v32, e32 = vals["fp32"]
-    e = np.abs(v32 - v64) / np.abs(v64)
-    out["fp32"]["rel_err_vs_fp64"] = {"median": float(f"{np.median(e):.3g}"), "p99": float(f"{np.percentile(e, 99):.3g}"),
-                                      "max": float(f"{e.max():.3g}")}
-    out["fp32"]["rel_err_estimate_covers"] = float(np.mean(e <= e32 + 1e-15))
+    vr, er = vals["ryser_fp64"]
+    # the Ryser sum has prod (M_k + 1) addends (no pivot row): its own flop count
+    ryser_add = sum(int(np.prod(np.asarray(M) + 1)) for _, M in items)
+    out["ryser_fp64"]["n_addends"] = ryser_add
+    out["ryser_fp64"]["gflops_graph"] = round(sum(
+        int(np.prod(np.asarray(M) + 1)) * (8 * A.shape[1] - (4 if all(int(m) == 1 for m in M) else 2))
+        for A, M in items) / (out["ryser_fp64"]["graph_ms"] * 1e-3) / 1e9, 1)
+    for k in ("gflops_wall", "pct_fp64_peak_wall", "addends_per_s"):
+        out["ryser_fp64"].pop(k, None)
+    ref = stored_oracle_c3(np)
+    if ref is not None:
+        for name, v, est in (("fp64", v64, e64), ("fp32", v32, e32), ("ryser_fp64", vr, er)):
+            e = np.abs(v - ref) / np.abs(ref)
+            out[name]["rel_err_vs_oracle"] = err_stats(np, e)
+            out[name]["rel_err_estimate_covers"] = float(np.mean(e <= est))
+        out["oracle_values"] = "tests/golden/c3_all.txt (double-double oracle, all 4096 items)"
     out["fp64"]["rel_err_estimate"] = {"median": float(f"{np.median(e64):.3g}"), "max": float(f"{e64.max():.3g}")}
     return out
 
 
-def serving_section(B, I, np, n_jobs: int, fracs=(0.25, 0.5, 0.75, 0.9, 1.1)):
+def accuracy_section(B, I, np):
+    """The engine comparison of Sec. 3.2 at n = 30: Eq. bbfg (perm_bbfg) and Eq. ryser
+    (perm_ryser) on the same FP64 walk against the stored double-double oracle values
+    (tests/golden/perm_golden.json), with each engine's conditioning kappa."""
+    try:
+        with open(os.path.join(ROOT, "tests", "golden", "perm_golden.json")) as fh:
+            golden = {c["name"]: c for c in json.load(fh)["cases"]}
+    except (OSError, ValueError):
+        return None
+    out = {}
+    for case in CASES:
+        g = golden.get("c2" + case)
+        if g is None:
+            continue
+        A = np.array([complex(a, b) for a, b in g["A"]]).reshape(g["rows"], g["cols"])
+        M = np.asarray(g["M"], dtype=np.int32)
+        ref = complex(g["re"][0] + g["re"][1], g["im"][0] + g["im"][1])
+        vb, ib = B.perm_bbfg(A, M, with_info=True)
+        vr, ir = B.perm_ryser(A, M, with_info=True)
+        out[case] = {"bbfg": {"rel_err": float(f"{abs(vb - ref) / abs(ref):.3g}"), "kappa": float(f"{ib['kappa']:.3g}"),
+                              "rel_err_est": float(f"{ib['rel_err_est']:.3g}"), "kernel_ms": round(ib["kernel_ms"], 3)},
+                     "ryser": {"rel_err": float(f"{abs(vr - ref) / abs(ref):.3g}"), "kappa": float(f"{ir['kappa']:.3g}"),
+                               "rel_err_est": float(f"{ir['rel_err_est']:.3g}"), "kernel_ms": round(ir["kernel_ms"], 3)}}
+    return out
+
+
+def serving_section(B, I, np, n_jobs: int, fracs=(0.25, 0.5, 0.75, 0.9, 1.1), poisson: bool = True):
     """Sampling jobs one at a time, all at once (capacity), then Poisson arrivals."""
     jobs = [I.c4_job(j) for j in range(n_jobs)]
     samples = sum(j[2] for j in jobs)
@@ -185,11 +251,18 @@ def serving_section(B, I, np, n_jobs: int, fracs=(0.25, 0.5, 0.75, 0.9, 1.1)):
         st = srv.stats()
     same = all(np.array_equal(r[0], s) for r, s in zip(res, solo))
     mu = n_jobs / t_burst
+    walk_s = st["walk_ms"] * 1e-3
     out["all_at_once"] = {"samples_per_s": round(samples / t_burst, 1), "makespan_s": round(t_burst, 3),
                           "speedup_vs_one_at_a_time": round(t_solo / t_burst, 3), "identical_to_alone": same,
-                          "max_active_jobs": int(st["max_active"]), "iterations": int(st["iterations"])}
+                          "max_active_jobs": int(st["max_active"]), "iterations": int(st["iterations"]),
+                          "minors_flops": float(f"{st['flops']:.4g}"),
+                          "minors_walk_s": round(walk_s, 4),
+                          "minors_tflops_walk": round(st["flops"] / walk_s / 1e12, 2) if walk_s > 0 else None,
+                          "minors_pct_fp64_peak_walk": round(100 * st["flops"] / walk_s / 1e12 / FP64_PEAK_TFLOPS, 2)
+                          if walk_s > 0 else None,
+                          "minors_tflops_makespan": round(st["flops"] / t_burst / 1e12, 2)}
     sweep = []
-    for idx, f in enumerate(fracs):
+    for idx, f in enumerate(fracs if poisson else ()):
         rate = f * mu
         arr = I.c4_arrivals(rate, n_jobs, idx)
         with B.Server() as srv:
@@ -224,9 +297,14 @@ def large_sampling_section(B, I, samples: int):
         t = time.perf_counter()
         s, info = B.bs_sample(U, occ, samples, loss, 5, with_info=True)
         dt = time.perf_counter() - t
-        out["lossy_0.5" if lossy else "ideal"] = {"s_per_sample": round(dt / samples, 4),
-                                                   "walk_ms": round(info["kernel_ms"], 1),
-                                                   "photons_out": s.sum(axis=1).tolist()}
+        walk_s = info["kernel_ms"] * 1e-3
+        out["lossy_0.5" if lossy else "ideal"] = {
+            "s_per_sample": round(dt / samples, 4), "walk_ms": round(info["kernel_ms"], 1),
+            "minors_tflops_walk": round(info["flops"] / walk_s / 1e12, 2) if walk_s > 0 else None,
+            "minors_pct_fp64_peak_walk": round(100 * info["flops"] / walk_s / 1e12 / FP64_PEAK_TFLOPS, 2)
+            if walk_s > 0 else None,
+            "err_est_max_per_sample": float(f"{info['rel_err_est']:.3g}"),
+            "photons_out": s.sum(axis=1).tolist()}
     return out
 
 
@@ -302,7 +380,11 @@ def main():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run one plain device-to-device copy of this size (HBM counter calibration)")
     ap.add_argument("--minors-probe", type=int, default=0,
-                    help="only run perm_minors on a K-column Haar minor (K - 1 rows, M = 1) ten times (kernel profiling)")
+                    help="only run perm_minors on a K-column Haar minor (K - 1 photons, M = 1) ten times (kernel profiling)")
+    ap.add_argument("--minors-bunch", type=int, default=0,
+                    help="with --minors-probe: the first B rows carry two photons (K - 1 - B rows)")
+    ap.add_argument("--probe-calls", type=int, default=10, help="calls of the minors probe")
+    ap.add_argument("--no-poisson", action="store_true", help="serving: skip the Poisson arrival sweep")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the permanent and sampler paths run on a single device "
@@ -327,13 +409,19 @@ def main():
         return
     B.init()
     if args.minors_probe:
-        K = args.minors_probe
-        A = torch.from_numpy(np.ascontiguousarray(I.haar_unitary(0)[:K - 1, :K])).to("cuda")
+        K, nb = args.minors_probe, args.minors_bunch
+        M = np.array([2] * nb + [1] * (K - 1 - 2 * nb), dtype=np.int32)
+        A = torch.from_numpy(np.ascontiguousarray(I.haar_unitary(0)[:len(M), :K])).to("cuda")
         ms = []
-        for _ in range(10):  # the last calls run at the sustained clock
-            B.perm_minors(A, np.ones(K - 1, dtype=np.int32))
+        for _ in range(args.probe_calls):  # the last calls run at the sustained clock
+            B.perm_minors(A, M)
             ms.append(round(B.batch_last_kernel_ms(), 4))
-        print(json.dumps({"minors_probe_columns": K, "n_addends_per_group": 2 ** (K - 2), "kernel_ms": ms}), flush=True)
+        cp = cprime_of(M)
+        fl = cp * (22 * K - (32 if nb else 36))  # all K minors
+        best = min(ms[-max(1, len(ms) // 2):])
+        print(json.dumps({"minors_probe_columns": K, "row_mult": M.tolist(), "n_addends": cp, "algorithmic_flops": fl,
+                          "kernel_ms": ms, "tflops_best_of_last_half": round(fl / best / 1e9, 2),
+                          "pct_fp64_peak": round(100 * fl / best / 1e9 / FP64_PEAK_TFLOPS, 2)}), flush=True)
         return
     inputs = {}
     for c in CASES:
@@ -398,15 +486,19 @@ def main():
             B.autotune(lo, hi, precision=prec)
             tuned[name] = {n: B.batch_unit_length(n, prec) for n in range(lo, hi + 1)}
         out["autotune"] = {"seconds": round(time.perf_counter() - t0, 2), "unit_length": tuned}
+    acc = accuracy_section(B, I, np)
+    if acc:
+        out["accuracy_bbfg_vs_ryser"] = acc
     if not args.no_batch:
         out["batch"] = batch_section(B, I, torch, np, args.batch_reps)
     if not args.no_serving:
-        sv = serving_section(B, I, np, args.serve_jobs)
+        sv = serving_section(B, I, np, args.serve_jobs, poisson=not args.no_poisson)
         out["serving"] = sv
-        near = min(sv["poisson"], key=lambda p: abs(p["load"] - 0.9))
         out["bs_samples_per_s"] = sv["all_at_once"]["samples_per_s"]
-        out["bs_p99_latency_s"] = near["latency_s_p99"]
-        out["bs_p99_at_load"] = near["load"]
+        if sv["poisson"]:
+            near = min(sv["poisson"], key=lambda p: abs(p["load"] - 0.9))
+            out["bs_p99_latency_s"] = near["latency_s_p99"]
+            out["bs_p99_at_load"] = near["load"]
     if args.large_samples > 0:
         out["large_sampling"] = large_sampling_section(B, I, args.large_samples)
     if not args.no_t0_fit:

@@ -65,8 +65,9 @@ typedef enum {
 
 /* BBFG_MINORS names the batched leave-one-column-out walks (FP64) in the
  * autotuner calls and bbfg_walk_occupancy; BBFG_COLS names the column-power
- * kernel in bbfg_walk_occupancy only. */
-typedef enum { BBFG_FP64 = 0, BBFG_FP32 = 1, BBFG_MINORS = 2, BBFG_COLS = 3 } bbfg_precision;
+ * kernel in bbfg_walk_occupancy only; BBFG_RYSER selects, in perm_batch, the
+ * FP64 Ryser formula over the same walk (the accuracy comparison of Sec. 3.2). */
+typedef enum { BBFG_FP64 = 0, BBFG_FP32 = 1, BBFG_MINORS = 2, BBFG_COLS = 3, BBFG_RYSER = 4 } bbfg_precision;
 
 typedef struct {
     double re, im;
@@ -79,6 +80,9 @@ typedef struct {
     uint64_t n_addends;  /* number of distinct addends C' = prod_k (M'_k + 1) (Sec. 2.2) */
     uint64_t n_units;    /* independent work units (one wavefront each) */
     double kernel_ms;    /* device time of the walk kernel, from HIP events on the library stream */
+    double flops;        /* algorithmic FP64 flops of the call's walks (an FMA counts 2): C' F per
+                          * permanent with F = 8n - 4 (all M = 1) or 8n - 2; per leave-one-column-out
+                          * addend over K columns F = 22K - 36 (all M = 1) or 22K - 32 */
 } bbfg_info;
 
 /* Thread-local description of the last error (never NULL). */
@@ -133,6 +137,27 @@ int perm_bbfg(const bbfg_c128 *A, int32_t n_rows, const int32_t *row_mult, int32
               bbfg_c128 *out, bbfg_info *info);
 
 /*
+ * perm_ryser -- the same permanent by Eq. (ryser) with row multiplicities, in
+ * FP64 over the same walk, for the accuracy comparison of Sec. 3.2 (Ryser's
+ * inner sums hold a varying number of matrix elements, so its addends span a
+ * wider range of magnitudes than those of Eq. bbfg):
+ *
+ *   perm(A, M) = (-1)^n sum_{s_k in [0, M_k]} (-1)^{sum s} prod_k C(M_k, s_k)
+ *                          prod_j sum_k s_k a_kj
+ *
+ * (subsets of the row copies; perm(A) = perm(A^T), so rows serve as well as
+ * the columns of Eq. ryser).  The walk has no pivot row: prod_k (M_k + 1)
+ * addends, 2^n for M = 1, twice those of perm_bbfg.  Every addend's column
+ * sums are walked as -2 sum_k s_k a_kj (an exact power-of-two scaling), the
+ * result is 2^{-n} times the walk's sum, and info->rel_err_est is the same
+ * estimate kappa * u * (n + sqrt(Q)) with Ryser's own kappa.
+ * Arguments and errors as perm_bbfg; BBFG_ERANGE also when the sum needs more
+ * than 2^32 work units (n = 48 with all M = 1).
+ */
+int perm_ryser(const bbfg_c128 *A, int32_t n_rows, const int32_t *row_mult, int32_t n_cols,
+               bbfg_c128 *out, bbfg_info *info);
+
+/*
  * perm_bbfg_noalloc -- perm_bbfg for callers that cannot allocate device
  * memory (tight serving loops, code that must not call hipMalloc).  Same
  * arguments, plan, kernels and result bits as perm_bbfg; every device buffer
@@ -165,9 +190,10 @@ int perm_bbfg_noalloc(const bbfg_c128 *A, int32_t n_rows, const int32_t *row_mul
  *   n_rows, n_cols   batch int32 shapes (host).
  *   row_mult_packed  int32 multiplicities (host); those of matrix b start at
  *                    row_mult_offset[b] (batch int64 offsets, host).
- *   precision        BBFG_FP64, or BBFG_FP32 (column sums and products in
+ *   precision        BBFG_FP64, BBFG_FP32 (column sums and products in
  *                    FP32, accumulation in FP64/double-double; every n_cols[b]
- *                    <= BBFG_MAX_N_FP32).
+ *                    <= BBFG_MAX_N_FP32), or BBFG_RYSER (FP64, the Ryser
+ *                    formula as perm_ryser evaluates it).
  *   out              batch bbfg_c128 results, host or device.
  *   rel_err_est      nullable, batch doubles (host): per-result error estimate.
  *
@@ -217,9 +243,10 @@ int perm_bbfg_cols(const bbfg_c128 *A, int32_t n_rows, const int32_t *row_mult, 
  *             out[l] = perm(A without column l, row_mult).
  *   rel_err_est  nullable, n_cols doubles (host): estimated relative error of
  *             out[l], kappa_l * u * (n + sqrt(Q)) with kappa_l the sum of
- *             |addend| of minor l over |out[l]|.  The magnitude sums are taken
- *             at every Gray position of sums up to 2^20 addends, and at every
- *             257th position (weighted by 257) of longer ones.
+ *             |addend| of minor l over |out[l]|.  The sum of |addend| is
+ *             estimated from one sample per lane and work unit (the addend's
+ *             modulus at the unit's last position times the unit's length):
+ *             within a factor of 8 of the exact kappa_l in the cases tested.
  *
  * FP64 with double-double reduction.  n_cols = 1 gives the empty permanent 1.
  * The walk is split to fill the device (as perm_bbfg splits a lone permanent),
@@ -377,6 +404,8 @@ typedef struct {
     double busy_s; /* worker time spent advancing samples (host preparation + device) */
     double host_s; /* part of busy_s spent preparing steps on the host (plans, metadata, launches) */
     double wait_s; /* part of busy_s spent waiting for the device to finish a step */
+    double flops;   /* algorithmic FP64 flops of the finished steps' walks (as bbfg_info.flops) */
+    double walk_ms; /* device time of those walks (HIP events around each step's walk kernel) */
 } bbfg_server_stats;
 int bs_server_stats(bbfg_server *srv, bbfg_server_stats *out);
 

@@ -25,6 +25,7 @@ BBFG_ECANCELED = -7
 BBFG_FP64 = 0
 BBFG_FP32 = 1
 BBFG_MINORS = 2
+BBFG_RYSER = 4
 BBFG_COLS = 3
 MAX_N = 48
 MAX_N_FP32 = 24
@@ -39,7 +40,7 @@ class BBFGError(RuntimeError):
 class Info(ctypes.Structure):
     _fields_ = [("rel_err_est", ctypes.c_double), ("kappa", ctypes.c_double),
                 ("n_addends", ctypes.c_uint64), ("n_units", ctypes.c_uint64),
-                ("kernel_ms", ctypes.c_double)]
+                ("kernel_ms", ctypes.c_double), ("flops", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -61,7 +62,8 @@ class ServerStats(ctypes.Structure):
                 ("iterations", ctypes.c_uint64), ("samples_done", ctypes.c_uint64),
                 ("max_active", ctypes.c_uint64), ("max_queued", ctypes.c_uint64),
                 ("jobs_cancelled", ctypes.c_uint64), ("busy_s", ctypes.c_double),
-                ("host_s", ctypes.c_double), ("wait_s", ctypes.c_double)]
+                ("host_s", ctypes.c_double), ("wait_s", ctypes.c_double), ("flops", ctypes.c_double),
+                ("walk_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -82,6 +84,7 @@ SIGNATURES = {
     "bbfg_set_cache_limits": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_uint64]),
     "perm_bbfg": (ctypes.c_int, [_P, _I32, _PI32, _I32, _P, ctypes.POINTER(Info)]),
     "perm_bbfg_noalloc": (ctypes.c_int, [_P, _I32, _PI32, _I32, _P, ctypes.POINTER(Info)]),
+    "perm_ryser": (ctypes.c_int, [_P, _I32, _PI32, _I32, _P, ctypes.POINTER(Info)]),
     "perm_batch": (ctypes.c_int, [_I32, _P, _PI64, _PI32, _PI32, _PI64, _PI32, _I32, _P, _PD]),
     "perm_minors": (ctypes.c_int, [_P, _I32, _PI32, _I32, _P, _PD]),
     "perm_bbfg_cols": (ctypes.c_int, [_P, _I32, _PI32, _I32, _PI32, _P, ctypes.POINTER(Info)]),
@@ -198,6 +201,18 @@ def perm_bbfg(A, row_mult=None, with_info: bool = False):
     out = np.zeros(1, dtype=np.complex128)
     info = Info()
     _check(lib().perm_bbfg(ptr, r, mp, n, ctypes.c_void_p(out.ctypes.data), ctypes.byref(info)))
+    del keep
+    return (complex(out[0]), info.as_dict()) if with_info else complex(out[0])
+
+
+def perm_ryser(A, row_mult=None, with_info: bool = False):
+    """The same permanent by Eq. (ryser) with row multiplicities, FP64, on the same walk."""
+    ptr, keep, shape = _cmat_ptr(A)
+    r, n = shape
+    mult, mp = _i32(np.ones(r, dtype=np.int32) if row_mult is None else row_mult)
+    out = np.zeros(1, dtype=np.complex128)
+    info = Info()
+    _check(lib().perm_ryser(ptr, r, mp, n, ctypes.c_void_p(out.ctypes.data), ctypes.byref(info)))
     del keep
     return (complex(out[0]), info.as_dict()) if with_info else complex(out[0])
 

@@ -8,6 +8,10 @@
 // random on 60 modes, as in the sampling workloads) is timed for each
 // candidate L and, among those within 2 % of the fastest per addend, the
 // longest is kept (the shortest for the minors kind).  Untuned n use a default.
+// Each candidate's timed launch of the plain kinds holds about 2^28 addends (at
+// most 16384 items, distinct matrices repeated; milliseconds at large n,
+// against tens of microseconds of launch noise).  Each candidate's rate comes
+// from the median of three launches after a warm-up launch.
 // The leave-one-column-out walks of the sampler (kind BBFG_MINORS) end every
 // unit with one reduction per target column, so they are tuned on their own.
 #include <algorithm>
@@ -80,10 +84,25 @@ try {
         std::vector<double> A;
         std::vector<int64_t> aoff, moff;
         std::vector<int32_t> rows, mult;
-        // about 2^31 addends per timed launch (at most 256 items, at least 2)
-        const int count = (int)std::max<int64_t>(2, std::min<int64_t>(256, (int64_t(1) << 31) >> (n - 1)));
+        // distinct synthetic items (an item of n photons on 60 modes has fewer
+        // than 2^{n-1} addends).  Plain kinds: repeated until the launch holds
+        // about 2^28 addends.  Minors: at most 256 items, as one sampling step
+        // of a batch of samples launches (short launches are what it runs).
+        const int distinct =
+            (int)std::max<int64_t>(2, std::min<int64_t>(minors ? 256 : 1024, (int64_t(1) << 31) >> (n - 1)));
         const int cols = minors ? n + 1 : n;
-        synthetic_batch(n, cols, count, 0x5eedULL * (uint64_t)n + (minors ? 7 : 0), A, aoff, rows, mult, moff);
+        synthetic_batch(n, cols, distinct, 0x5eedULL * (uint64_t)n + (minors ? 7 : 0), A, aoff, rows, mult, moff);
+        int count = distinct;
+        if (!minors) {
+            uint64_t per = 0;
+            for (int i = 0; i < distinct; ++i) {
+                std::shared_ptr<const HostPlan> pl;
+                BBFG_TRY(get_plan(*c, mult.data() + moff[(size_t)i], rows[(size_t)i], n, kind, PLAN_BATCH, &pl));
+                per += pl->n_addends;
+            }
+            const double want = std::ldexp(1.0, 28) / (double)std::max<uint64_t>(1, per) * distinct;
+            count = (int)std::min(16384.0, std::max((double)distinct, std::ceil(want)));
+        }
         DevBuf dA;
         BBFG_TRY(dA.ensure(sizeof(double) * A.size()));
         BBFG_HIP(hipMemcpyAsync(dA.p, A.data(), sizeof(double) * A.size(), hipMemcpyHostToDevice, s));
@@ -96,7 +115,8 @@ try {
             std::deque<std::vector<int32_t>> keep;
             std::vector<uint32_t> slot((size_t)cols);
             uint64_t addends = 0, nres = 0;
-            for (int i = 0; i < count; ++i) {
+            for (int rep_item = 0; rep_item < count; ++rep_item) {
+                const int i = rep_item % distinct;
                 PermItem it;
                 it.src = dA.as<double>();
                 it.src_off = (uint64_t)aoff[(size_t)i];
@@ -117,13 +137,14 @@ try {
                     items.push_back(std::move(it));
                 }
             }
-            double ms_best = 1e300;
-            for (int rep = 0; rep < 3; ++rep) {
+            std::vector<double> ms;
+            for (int rep = 0; rep < 4; ++rep) {
                 RunResult rr;
                 BBFG_TRY(run_perms(*c, items, f32, false, nullptr, nullptr, &rr));
-                ms_best = std::min(ms_best, rr.kernel_ms);
+                if (rep > 0) ms.push_back(rr.kernel_ms);  // the first launch brings tables and clocks up
             }
-            rates.push_back({L, (double)addends / ms_best});
+            std::sort(ms.begin(), ms.end());
+            rates.push_back({L, (double)addends / ms[ms.size() / 2]});
         }
         // Within 2 % of the best rate: plain batches take the longest unit (fewer
         // units, less per-unit reduction), the sampler's minors the shortest (its

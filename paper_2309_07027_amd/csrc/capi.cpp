@@ -75,9 +75,15 @@ int bbfg_set_stream(void* hip_stream)
     return BBFG_OK;
 }
 
-int perm_bbfg(const bbfg_c128* A, int32_t n_rows, const int32_t* row_mult, int32_t n_cols, bbfg_c128* out,
-              bbfg_info* info)
-try {
+}  // extern "C"
+
+namespace {
+
+// One permanent in one launch that fills the device: Eq. bbfgrepeated, or
+// Eq. ryser with row multiplicities (ryser), over the same walk.
+int single_perm(const bbfg_c128* A, int32_t n_rows, const int32_t* row_mult, int32_t n_cols, bbfg_c128* out,
+                bbfg_info* info, bool ryser)
+{
     if (!out) return set_error(BBFG_EINVAL, "out is NULL");
     BBFG_TRY(validate_shape(row_mult, n_rows, n_cols, kMaxN));
     if (n_cols > 0 && !A) return set_error(BBFG_EINVAL, "A is NULL");
@@ -102,18 +108,38 @@ try {
     items[0].n_rows = n_rows;
     items[0].n = n_cols;
     items[0].mult = row_mult;
-    BBFG_TRY(get_plan(*c, row_mult, n_rows, n_cols, 0, PLAN_SINGLE, &items[0].plan));
+    BBFG_TRY(get_plan(*c, row_mult, n_rows, n_cols, 0, PLAN_SINGLE, &items[0].plan, 0, ryser));
     double res[2], diag[2];
     RunResult rr;
     BBFG_TRY(run_perms(*c, items, 0, true, res, diag, &rr));
     if (info) {
+        bool mult = false;
+        for (int32_t i = 0; i < n_rows; ++i) mult = mult || row_mult[i] > 1;
         info->rel_err_est = diag[0];
         info->kappa = diag[1];
         info->n_addends = items[0].plan->n_addends;
         info->n_units = rr.units;
         info->kernel_ms = rr.kernel_ms;
+        info->flops = (double)items[0].plan->n_addends * walk_flops(n_cols, mult);
     }
     return write_results(out, res, 1);
+}
+
+}  // namespace
+
+extern "C" {
+
+int perm_bbfg(const bbfg_c128* A, int32_t n_rows, const int32_t* row_mult, int32_t n_cols, bbfg_c128* out,
+              bbfg_info* info)
+try {
+    return single_perm(A, n_rows, row_mult, n_cols, out, info, false);
+}
+BBFG_API_CATCH
+
+int perm_ryser(const bbfg_c128* A, int32_t n_rows, const int32_t* row_mult, int32_t n_cols, bbfg_c128* out,
+               bbfg_info* info)
+try {
+    return single_perm(A, n_rows, row_mult, n_cols, out, info, true);
 }
 BBFG_API_CATCH
 
@@ -125,9 +151,10 @@ try {
     if (batch == 0) return BBFG_OK;
     if (!out || !A_offset || !n_rows || !row_mult_offset || !n_cols)
         return set_error(BBFG_EINVAL, "NULL array argument");
-    if (precision != BBFG_FP64 && precision != BBFG_FP32)
-        return set_error(BBFG_EINVAL, "precision = %d is neither BBFG_FP64 nor BBFG_FP32", precision);
+    if (precision != BBFG_FP64 && precision != BBFG_FP32 && precision != BBFG_RYSER)
+        return set_error(BBFG_EINVAL, "precision = %d is none of BBFG_FP64, BBFG_FP32, BBFG_RYSER", precision);
     const int f32 = precision == BBFG_FP32 ? 1 : 0;
+    const bool ryser = precision == BBFG_RYSER;
     const int max_n = f32 ? kMaxNF32 : kMaxN;
     uint64_t extent = 0;
     bool any = false;
@@ -158,7 +185,7 @@ try {
         for (int32_t b = 0; b < batch; ++b)
             if (n_cols[b] > 0) flat.insert(flat.end(), row_mult_packed + row_mult_offset[b],
                                            row_mult_packed + row_mult_offset[b] + n_rows[b]);
-        const bool hit = memo.epoch == c->plan_epoch && memo.f32 == f32 && memo.n_rows.size() == (size_t)batch &&
+        const bool hit = memo.epoch == c->plan_epoch && memo.f32 == precision && memo.n_rows.size() == (size_t)batch &&
                          std::equal(memo.n_rows.begin(), memo.n_rows.end(), n_rows) &&
                          std::equal(memo.n_cols.begin(), memo.n_cols.end(), n_cols) && memo.mult == flat;
         std::vector<PermItem> items;
@@ -174,13 +201,13 @@ try {
             it.n = n_cols[b];
             it.mult = row_mult_packed + row_mult_offset[b];
             if (hit) it.plan = memo.plans[items.size()];
-            else BBFG_TRY(get_plan(*c, it.mult, it.n_rows, it.n, f32, PLAN_BATCH, &it.plan));
+            else BBFG_TRY(get_plan(*c, it.mult, it.n_rows, it.n, f32, PLAN_BATCH, &it.plan, 0, ryser));
             items.push_back(std::move(it));
             idx.push_back(b);
         }
         if (!hit) {
             memo.epoch = c->plan_epoch;
-            memo.f32 = f32;
+            memo.f32 = precision;
             memo.n_rows.assign(n_rows, n_rows + batch);
             memo.n_cols.assign(n_cols, n_cols + batch);
             memo.mult.swap(flat);
@@ -322,11 +349,22 @@ try {
     RunResult rr;
     BBFG_TRY(run_perms(*c, items, 0, single, res, diag, &rr));
     if (info) {
+        bool mult = false;
+        for (int32_t i = 0; i < n_rows; ++i) mult = mult || row_mult[i] > 1;
         info->rel_err_est = diag[0];
         info->kappa = diag[1];
         info->n_addends = it.plan->n_addends;
         info->n_units = rr.units;
         info->kernel_ms = rr.kernel_ms;
+        // C distinct column sums and C - 1 products, then (.)^e by binary powering
+        const int C = it.arena_cols > 0 ? it.arena_cols : (int)n;
+        int pw = 0;
+        if (it.col_pow >= 2) {
+            int top = 31;
+            while (!((it.col_pow >> top) & 1)) --top;
+            pw = top + __builtin_popcount((unsigned)it.col_pow) - 1;
+        }
+        info->flops = (double)it.plan->n_addends * (8.0 * C - 4.0 + 6.0 * pw + (mult ? 2.0 : 0.0));
     }
     return write_results(out, res, 1);
 }

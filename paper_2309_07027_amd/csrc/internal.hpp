@@ -65,19 +65,9 @@ struct PermDesc {
     uint32_t res_base;       // index of the first result
     uint32_t col_pow;        // every one of the n (distinct) columns has multiplicity col_pow
                              //   (Eq. bbfgrepeated): the product is (prod_j c_j)^col_pow
-    uint32_t mag_stride;     // leave-one-column-out walks: the magnitude sum of each target is
-                             //   taken over the positions lin = 0 mod mag_stride of a lane's range
-                             //   and weighted by mag_stride (1: every position)
+    uint32_t mag_every;      // leave-one-column-out walks: units whose index in their lane group is
+                             //   a multiple of mag_every sample the magnitude estimate (>= 1)
 };
-
-// Leave-one-column-out walks accumulate the magnitudes of each target's
-// addends (for the error estimate) at every position of sums up to
-// kMagExactAddends addends, and at every kMagStride-th position of longer ones
-// (at least 4096 samples per target).  The stride is a prime above every Gray
-// radix (M + 1 <= 49), so the sampled positions do not follow the digit
-// pattern; a sampled step leaves the walk's inner loop, so it is kept rare.
-constexpr uint64_t kMagExactAddends = uint64_t(1) << 20;
-constexpr uint32_t kMagStride = 257;
 
 // Leave-one-column-out walks over K columns cover the targets in groups of
 // minor_group(K): one group keeps K column sums, G prefix products and G
@@ -100,12 +90,13 @@ constexpr int minor_group(int K)
     return (K + groups - 1) / groups;
 }
 
-// Most targets of one leave-one-column-out walk over at most KMAX columns.
-constexpr int max_minor_group(int KMAX)
+// Leave-one-column-out walks estimate each target's sum of |addend| from about
+// this many sampled units per lane group (64 lanes each), all units if fewer.
+constexpr uint64_t kMagUnitsPerGroup = 32;
+inline uint32_t mag_every_for(uint64_t units_per_group)
 {
-    int g = 1;
-    for (int K = 2; K <= KMAX; ++K) g = minor_group(K) > g ? minor_group(K) : g;
-    return g;
+    const uint64_t e = units_per_group / kMagUnitsPerGroup;
+    return e > 1 ? (uint32_t)e : 1u;
 }
 
 constexpr uint32_t kUnitChunkLog2 = 6;

@@ -17,12 +17,11 @@ int minors_bucket_max(int nmax);
 
 hipError_t launch_walk_single(int n, int f32, uint32_t grid, hipStream_t s, const WalkArgs& A, uint32_t item);
 hipError_t launch_walk_batch(int bucket, int f32, uint32_t grid, hipStream_t s, const WalkArgs& A);
-// uniform column multiplicities (items with col_pow >= 2), FP64, same buckets
+// uniform column multiplicities (items with col_pow >= 2), FP64, buckets 16 and
+// 24 (at most 24 distinct columns)
 const void* walk_cols_fn(int bucket);
 const void* walk_cols_fn_b16();
 const void* walk_cols_fn_b24();
-const void* walk_cols_fn_b32();
-const void* walk_cols_fn_b48();
 hipError_t launch_walk_cols(int bucket, uint32_t grid, hipStream_t s, const WalkArgs& A);
 // leave-one-column-out walks (items with targets > 0), FP64, same buckets
 const void* walk_minors_fn(int bucket);

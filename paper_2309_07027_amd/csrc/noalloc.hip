@@ -193,10 +193,10 @@ try {
     d.Q = P.Q;
     d.lane_product = P.lane_product;
     d.groups = P.groups;
-    d.scale = std::ldexp(1.0, 1 - n);
+    d.scale = std::ldexp(1.0, P.scale_log2);
     d.err_coeff = P.err_coeff * 0x1.0p-53;
     d.col_pow = 1;
-    d.mag_stride = 1;
+    d.mag_every = 1;
     std::memcpy(H + o_row, P.rows.data(), sizeof(RowInfo) * (size_t)r);
     PrepItem& q = *reinterpret_cast<PrepItem*>(H + o_prep);
     q.src = src;
@@ -236,8 +236,11 @@ try {
     if (info) {
         info->rel_err_est = host_res[2];
         info->kappa = host_res[3];
+        bool mult = false;
+        for (int32_t i = 0; i < n_rows; ++i) mult = mult || row_mult[i] > 1;
         info->n_addends = P.n_addends;
         info->n_units = P.units;
+        info->flops = (double)P.n_addends * walk_flops(n_cols, mult);
     }
     return BBFG_OK;
 }

@@ -172,17 +172,24 @@ int build_plan(const int32_t* mult, int n_rows, int n_cols, uint64_t slots, cons
     if (P.n == 0) return BBFG_OK;
 
     // pivot: first kept row with the smallest multiplicity (Sec. 2.2 moves a
-    // non-repeated row to the top when one exists)
-    P.pivot = 0;
-    for (int k = 1; k < P.r; ++k)
-        if (P.mult[(size_t)k] < P.mult[(size_t)P.pivot]) P.pivot = k;
+    // non-repeated row to the top when one exists).  The Ryser sum has none:
+    // every row copy is in or out of the subset.
+    P.pivot = -1;
+    if (!pp.ryser) {
+        P.pivot = 0;
+        for (int k = 1; k < P.r; ++k)
+            if (P.mult[(size_t)k] < P.mult[(size_t)P.pivot]) P.pivot = k;
+    }
+    // BB/FG: 2^{1-n} times the walk; Ryser: the walk's column sums are -2 times
+    // the subset sums, and (-1)^n (-2)^{-n} = 2^{-n}
+    P.scale_log2 = pp.ryser ? -P.n : 1 - P.n;
 
     P.rows.resize((size_t)P.r);
     std::vector<int> digits;
     for (int k = 0; k < P.r; ++k) {
         RowInfo& x = P.rows[(size_t)k];
         x.mp = P.mult[(size_t)k] - (k == P.pivot ? 1 : 0);
-        x.base = x.mp + (k == P.pivot ? 1 : 0);
+        x.base = pp.ryser ? 0 : x.mp + (k == P.pivot ? 1 : 0);
         x.radix = (uint32_t)x.mp + 1u;
         x.stride = 1;
         x.kind = ROW_FIXED;
@@ -261,7 +268,7 @@ int build_plan(const int32_t* mult, int n_rows, int n_cols, uint64_t slots, cons
         P.src_row.swap(src_row);
         P.mult.swap(mult_k);
         P.rows.swap(rows);
-        P.pivot = new_index[(size_t)P.pivot];
+        if (P.pivot >= 0) P.pivot = new_index[(size_t)P.pivot];
         for (auto* v : {&P.lane_digits, &P.low_digits, &P.high_digits})
             for (int& k : *v) k = new_index[(size_t)k];
     }

@@ -20,6 +20,10 @@ struct PlanParams {
     // batched launches: units of a fixed length, so an item's split depends on its
     // own shape only (0 = use the single-launch rule)
     uint64_t l_batch = 0;
+    // Eq. ryser with row multiplicities instead of Eq. bbfgrepeated: every kept
+    // row is a digit s_k in [0, M_k] (no pivot), column sums sum_k s_k a_kj
+    // (walked as base 0, coefficient -2 s_k), weight (-1)^{s_k} C(M_k, s_k)
+    bool ryser = false;
 };
 
 using TablePtr = std::shared_ptr<const std::vector<TabEntry>>;
@@ -57,6 +61,7 @@ struct HostPlan {
     uint64_t units = 1;
     uint64_t n_addends = 1;        // C'
     double err_coeff = 1.0;
+    int scale_log2 = 0;            // the walk's sum times 2^scale_log2 is the permanent
     std::vector<uint32_t> low_radix;  // radices of the low digits (table key)
     TablePtr table;                // Q entries
 };

@@ -237,14 +237,16 @@ int load_autotune_file(Context& c, const char* path)
 }
 
 int get_plan(Context& c, const int32_t* mult, int n_rows, int n_cols, int f32, int mode,
-             std::shared_ptr<const HostPlan>* out, int kernel_cols)
+             std::shared_ptr<const HostPlan>* out, int kernel_cols, bool ryser)
 {
     PlanParams pp = c.params;
+    pp.ryser = ryser;
     if (mode == PLAN_BATCH) pp.l_batch = batch_unit_length(c, n_cols, f32);
     std::string key;
     key.reserve(32 + 4 * (size_t)n_rows);
     key.append(reinterpret_cast<const char*>(&n_cols), sizeof n_cols);
     key.push_back((char)f32);
+    key.push_back(ryser ? 'R' : 'G');
     key.append(reinterpret_cast<const char*>(&pp.l_batch), sizeof pp.l_batch);
     key.append(reinterpret_cast<const char*>(&kernel_cols), sizeof kernel_cols);
     key.append(reinterpret_cast<const char*>(mult), sizeof(int32_t) * (size_t)n_rows);
@@ -472,13 +474,13 @@ int run_perms(Context& c, Workspace& w, std::vector<PermItem>& items, int f32, b
         d.Q = p.Q;
         d.lane_product = p.lane_product;
         d.groups = p.groups;
-        d.scale = std::ldexp(1.0, 1 - p.n);
+        d.scale = std::ldexp(1.0, p.scale_log2);
         d.err_coeff = p.err_coeff * (f32 ? 0x1.0p-24 : 0x1.0p-53);
         d.part_base = part_base[i];
         d.targets = (uint32_t)items[i].targets;
         d.res_base = res_base[i];
         d.col_pow = items[i].col_pow >= 2 ? (uint32_t)items[i].col_pow : 1u;
-        d.mag_stride = (items[i].targets > 0 && p.n_addends > kMagExactAddends) ? kMagStride : 1u;
+        d.mag_every = mag_every_for(p.units_per_group);
         for (uint64_t t = 0; t < stride_of(items[i]); ++t) hri[res_base[i] + t] = (uint32_t)i;
         PrepItem& q = hp[i];
         std::memset(&q, 0, sizeof q);

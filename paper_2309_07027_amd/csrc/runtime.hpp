@@ -26,6 +26,14 @@ namespace bbfg {
 // ---- errors (thread-local message) ----------------------------------------
 int set_error(int code, const char* fmt, ...);
 const char* last_error();
+// Algorithmic FP64 flops per addend (an FMA counts 2): the walk of n columns
+// (2n column-sum adds, n - 1 complex products, the accumulate, and the weight
+// when some M > 1), and a leave-one-column-out walk over K columns (K sums, the
+// prefix, suffix and combining products of the K minors, 3(K - 2), the K
+// accumulates, and the weight on both product chains when some M > 1).
+inline double walk_flops(int n, bool mult) { return 8.0 * n - (mult ? 2.0 : 4.0); }
+inline double minors_flops(int K, bool mult) { return 22.0 * K - (mult ? 32.0 : 36.0); }
+
 // Host-side validation of one matrix shape (before any device work).
 int validate_shape(const int32_t* mult, int32_t n_rows, int32_t n_cols, int max_n);
 
@@ -145,7 +153,7 @@ struct Context {
     // and multiplicities reuses its plans without a lookup per item
     struct BatchMemo {
         uint64_t epoch = ~0ull;
-        int f32 = -1;
+        int f32 = -1;  // the precision argument of the batch
         std::vector<int32_t> n_rows, n_cols, mult;
         std::vector<std::shared_ptr<const HostPlan>> plans;
     } batch_memo;
@@ -184,8 +192,9 @@ int batch_waves(Context& c, int bucket, int kind, int* waves);
 // the plain walk for n_cols columns, the minors kernel for n_cols + 1 columns
 // (kind kKindMinors), or the column-power kernel for kernel_cols distinct
 // columns (kind kKindCols).
+// ryser: the plan of Eq. ryser with row multiplicities (no pivot, base 0).
 int get_plan(Context& c, const int32_t* mult, int n_rows, int n_cols, int kind, int mode,
-             std::shared_ptr<const HostPlan>* out, int kernel_cols = 0);
+             std::shared_ptr<const HostPlan>* out, int kernel_cols = 0, bool ryser = false);
 // Pool space for a device table of `bytes` bytes (resident until a flush).
 int table_reserve(Context& c, size_t bytes, TabEntry** out);
 // Caches are bounded (Context::plan_cap, Context::table_entry_cap): past these

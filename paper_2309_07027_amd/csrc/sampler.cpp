@@ -293,6 +293,9 @@ int cc_step_begin(Context& c, Workspace& w, std::vector<ActiveSample>& act, CCPe
             add_minor_items(proto, S.pi.data(), keep, items, nres, slots.data() + st.minor_off);
             for (size_t i = first; i < items.size(); ++i) nres += (uint64_t)items[i].targets;
             if (addends) *addends += (uint64_t)k * proto.plan->n_addends;
+            bool bunched = false;
+            for (int32_t x : mult) bunched = bunched || x > 1;
+            p.flops += (double)proto.plan->n_addends * minors_flops(k, bunched);
         }
         steps.push_back(st);
         act_of_step.push_back(ai);
@@ -331,7 +334,7 @@ int cc_step_begin(Context& c, Workspace& w, std::vector<ActiveSample>& act, CCPe
     return BBFG_OK;
 }
 
-int cc_step_end(Workspace& w, std::vector<ActiveSample>& act, CCPending& p, double* kernel_ms)
+int cc_step_end(Workspace& w, std::vector<ActiveSample>& act, CCPending& p, double* kernel_ms, double* flops)
 {
     if (!p.queued) return BBFG_OK;
     p.queued = false;
@@ -341,6 +344,7 @@ int cc_step_end(Workspace& w, std::vector<ActiveSample>& act, CCPending& p, doub
         BBFG_HIP(hipEventElapsedTime(&ms, w.ev0, w.ev1));
         *kernel_ms += ms;
     }
+    if (flops) *flops += p.flops;
     const int32_t* drawn = reinterpret_cast<const int32_t*>(w.cc_hmeta.as<char>() + p.o_drawn);
     const double* tv = reinterpret_cast<const double*>(w.cc_hmeta.as<char>() + p.o_tv);
     for (size_t i = 0; i < p.act_of_step.size(); ++i) {
@@ -355,14 +359,14 @@ int cc_step_end(Workspace& w, std::vector<ActiveSample>& act, CCPending& p, doub
 }
 
 int cc_step(Context& c, std::vector<ActiveSample>& act, double* kernel_ms, uint64_t* addends, double* host_s,
-            double* wait_s)
+            double* wait_s, double* flops)
 {
     using Clock = std::chrono::steady_clock;
     const auto t0 = Clock::now();
     CCPending p;
     BBFG_TRY(cc_step_begin(c, c.ws, act, p, addends));
     const auto t1 = Clock::now();
-    BBFG_TRY(cc_step_end(c.ws, act, p, kernel_ms));
+    BBFG_TRY(cc_step_end(c.ws, act, p, kernel_ms, flops));
     if (host_s) *host_s += std::chrono::duration<double>(t1 - t0).count();
     if (wait_s) *wait_s += std::chrono::duration<double>(Clock::now() - t1).count();
     return BBFG_OK;
@@ -378,7 +382,7 @@ namespace {
 int run_job(Context& c, CCJob& job, int32_t* out_occupation, bbfg_info* info)
 {
     constexpr int kWaveSamples = 1024;
-    double kms = 0.0;
+    double kms = 0.0, fl = 0.0;
     uint64_t adds = 0;
     for (int s0 = 0; s0 < job.n_samples; s0 += kWaveSamples) {
         const int s1 = std::min(job.n_samples, s0 + kWaveSamples);
@@ -387,13 +391,14 @@ int run_job(Context& c, CCJob& job, int32_t* out_occupation, bbfg_info* info)
             cc_start_sample(job, s);
             act.push_back({&job, s});
         }
-        for (int k = 1; k <= job.n; ++k) BBFG_TRY(cc_step(c, act, &kms, &adds));
+        for (int k = 1; k <= job.n; ++k) BBFG_TRY(cc_step(c, act, &kms, &adds, nullptr, nullptr, &fl));
     }
     std::memcpy(out_occupation, job.out.data(), sizeof(int32_t) * job.out.size());
     if (info) {
         info->kernel_ms = kms;
         info->n_addends = adds;
         info->rel_err_est = job.tv_max;
+        info->flops = fl;
     }
     return BBFG_OK;
 }

@@ -105,15 +105,18 @@ struct CCPending {
     size_t o_drawn = 0;               // offset of the draws in w.cc_hmeta
     size_t o_tv = 0;                  // offset of the steps' error estimates in w.cc_hmeta
     bool has_items = false;           // a minors launch was queued (timed by w.ev0/ev1)
+    double flops = 0.0;               // algorithmic flops of the queued minors walks
     bool queued = false;
 };
 int cc_step_begin(Context& c, Workspace& w, std::vector<ActiveSample>& act, CCPending& p, uint64_t* addends);
-int cc_step_end(Workspace& w, std::vector<ActiveSample>& act, CCPending& p, double* kernel_ms);
+// kernel_ms / flops (nullable) accumulate the step's walk time and algorithmic flops.
+int cc_step_end(Workspace& w, std::vector<ActiveSample>& act, CCPending& p, double* kernel_ms,
+                double* flops = nullptr);
 
 // Both halves back to back in the context's workspace.  host_s / wait_s
 // (nullable) accumulate the seconds spent preparing the step on the host and
 // waiting for the device.
 int cc_step(Context& c, std::vector<ActiveSample>& act, double* kernel_ms, uint64_t* addends,
-            double* host_s = nullptr, double* wait_s = nullptr);
+            double* host_s = nullptr, double* wait_s = nullptr, double* flops = nullptr);
 
 }  // namespace bbfg

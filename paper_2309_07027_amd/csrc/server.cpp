@@ -163,12 +163,15 @@ void bbfg_server::run()
         int rc = BBFG_OK;
         // 1. the draws of this half's step in flight
         if (h.pend.queued) {
-            rc = cc_step_end(h.ws, h.act, h.pend, nullptr);
+            double wms = 0.0, fl = 0.0;
+            rc = cc_step_end(h.ws, h.act, h.pend, &wms, &fl);
             const double dt = std::chrono::duration<double>(Clock::now() - t0).count();
             std::lock_guard<std::mutex> lk(mu);
             st.wait_s += dt;
             st.busy_s += dt;
             st.iterations++;
+            st.walk_ms += wms;
+            st.flops += fl;
         }
         if (rc != BBFG_OK) {
             half[0].pend.queued = half[1].pend.queued = false;

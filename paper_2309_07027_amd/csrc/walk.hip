@@ -220,13 +220,13 @@ const void* walk_batch_fn(int bucket, int f32)
     }
 }
 
+// Column-power items have every distinct column at multiplicity >= 2, so at
+// most BBFG_MAX_N / 2 = 24 distinct columns: two buckets.
 const void* walk_cols_fn(int bucket)
 {
     switch (bucket) {
     case 16: return walk_cols_fn_b16();
     case 24: return walk_cols_fn_b24();
-    case 32: return walk_cols_fn_b32();
-    case 48: return walk_cols_fn_b48();
     default: return nullptr;
     }
 }

@@ -28,19 +28,16 @@ BBFG_FN kptr<T> kconst(const T* p)
     return (kptr<T>)p;
 }
 BBFG_FN uint32_t uniform_u32(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
-// *p += v for a lane's own LDS slot, as an atomic without return value
-// (ds_add_f64): the walk issues it and moves on, holding no register for a
-// load of the old value
-BBFG_FN void lds_add(double* p, double v)
-{
-    (void)__hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-}
+// 1/sqrt(x) from the hardware's approximate reciprocal square root (for
+// estimates only)
+BBFG_FN double approx_rsqrt(double x) { return __builtin_amdgcn_rsq(x); }
 }  // namespace bbfg
 #else
 #define BBFG_FN inline
 #include "emu_ptr.hpp"
+#include <cmath>
 namespace bbfg {
-inline void lds_add(double* p, double v) { *p += v; }
+inline double approx_rsqrt(double x) { return 1.0 / std::sqrt(x); }
 }  // namespace bbfg
 #endif
 
@@ -304,12 +301,8 @@ BBFG_FN void walk_unit(const WalkArgs& A, const PermDesc& d, uint32_t u_local, u
 // The weight ws enters the first prefix product, so each target's update is
 // one complex multiply-accumulate of its prefix and suffix products: four
 // fused multiply-adds instead of a complex product and a weighted add.
-// MAG: also mag[t * mag_step] += mag_w * (|Re x| + |Im x|) for target t's
-// addend x, between its modulus and sqrt(2) times it (mag is a lane's own LDS
-// slots on the device).
-template <int K, int G, typename Real, bool MAG = false>
-BBFG_FN void minors_accumulate(const Real* re, const Real* im, double ws, double* accr, double* acci,
-                               double* mag = nullptr, uint32_t mag_step = 1, double mag_w = 0.0)
+template <int K, int G, typename Real>
+BBFG_FN void minors_accumulate(const Real* re, const Real* im, double ws, double* accr, double* acci)
 {
     constexpr int T = K - G;
     Real pr[G], pim[G];
@@ -330,18 +323,10 @@ BBFG_FN void minors_accumulate(const Real* re, const Real* im, double ws, double
         if (t == G - 1) {
             accr[t] = accr[t] + (double)pr[t];
             acci[t] = acci[t] + (double)pim[t];
-            if constexpr (MAG) lds_add(mag + t * mag_step, mag_w * (__builtin_fabs((double)pr[t]) + __builtin_fabs((double)pim[t])));
         } else {
             const double ar = (double)pr[t], ai = (double)pim[t], br = (double)sr, bi = (double)si;
             accr[t] = __builtin_fma(-ai, bi, __builtin_fma(ar, br, accr[t]));
             acci[t] = __builtin_fma(ai, br, __builtin_fma(ar, bi, acci[t]));
-            if constexpr (MAG) {
-                // the addend itself (prefix times suffix), so that nothing of it
-                // can be formed before the suffix exists
-                const double xr = __builtin_fma(ar, br, -(ai * bi));
-                const double xi = __builtin_fma(ar, bi, ai * br);
-                lds_add(mag + t * mag_step, mag_w * (__builtin_fabs(xr) + __builtin_fabs(xi)));
-            }
         }
         if (t > 0) {
             if (t == G - 1) {
@@ -362,22 +347,31 @@ BBFG_FN void minors_accumulate(const Real* re, const Real* im, double ws, double
 // of the permanents (size K - 1) that each drop one of the last G columns.
 // The walk over the rows is the one of walk_unit; the signed weight w * s is
 // an integer below 2^53 (a product of binomials), hence exact.
-// mag[t * mag_step] receives the lane's estimate of the sum of |addend| of
-// target t: the positions of the lane's range whose index is a multiple of
-// d.mag_stride, each counted d.mag_stride times (every position when the
-// stride is 1).  The caller provides the G slots (the kernel keeps them in
-// LDS, off the register file).
-template <int K, int G, typename Real>
-BBFG_FN void walk_minors_unit(const WalkArgs& A, const PermDesc& d, uint32_t u_local, uint32_t lane, double* out_r,
-                              double* out_i, double* mag, uint32_t mag_step)
+// After the walk, sink.sum(t, re_t, im_t) hands over target t's sums.  Then
+// units whose index in the lane group is a multiple of d.mag_every call
+// sink.mag(t, a_t) with the lane's estimate of the sum of |addend| of target t
+// over its positions in this unit and the d.mag_every - 1 units after it: the
+// modulus of the addend at the unit's last position,
+//   |w s| prod_{j != K-G+t} |c_j| = |w s| sqrt(P2) / |c_{K-G+t}|,
+// P2 the product of all K squared moduli, times the unit's number of
+// positions and the number of units it stands for (one sample per lane, from
+// column sums seeded afresh at that position, so the walk loop carries no
+// extra work or registers; the reciprocal square roots are the hardware's
+// approximation); the other units call sink.no_mag(t).  a_t is 0 where target
+// t's own column sum is exactly zero.  The passes over the targets are
+// separate loops, each small enough to be unrolled in full.
+template <int K, int G, typename Real, typename Sink>
+BBFG_FN void walk_minors_unit(const WalkArgs& A, const PermDesc& d, uint32_t u_local, uint32_t lane, Sink& sink)
 {
+    constexpr int T = K - G;
     const uint32_t upg = (uint32_t)d.units_per_group;
     const uint32_t g = u_local / upg;
     const uint32_t part = u_local - g * upg;
     const uint64_t base = d.span / upg;
     const uint32_t rem = (uint32_t)(d.span - base * upg);
-    uint64_t lin = (uint64_t)part * base + (part < rem ? part : rem);
-    const uint64_t lin1 = lin + base + (part < rem ? 1u : 0u);
+    const uint64_t lin0 = (uint64_t)part * base + (part < rem ? part : rem);
+    const uint64_t lin1 = lin0 + base + (part < rem ? 1u : 0u);
+    uint64_t lin = lin0;
     uint32_t lane_idx = g * kWave + lane;
     const bool valid = lane_idx < d.lane_product;
     if (!valid) lane_idx = 0;
@@ -385,16 +379,12 @@ BBFG_FN void walk_minors_unit(const WalkArgs& A, const PermDesc& d, uint32_t u_l
     kptr<TabEntry> tab = kconst(d.tab);
     kptr<Real> a2 = kconst(RowsOf<Real>::a2(A) + 2 * d.a2_off);
     const uint32_t Q = d.Q;
-    const uint32_t mstride = uniform_u32(d.mag_stride);
-    const double mag_w = (double)mstride;
-    // positions until the next sampled one (0: this one)
-    uint32_t mwait = uniform_u32((uint32_t)((mstride - lin % mstride) % mstride));
 
+    double out_r[G], out_i[G];
 #pragma unroll
     for (int t = 0; t < G; ++t) {
         out_r[t] = 0.0;
         out_i[t] = 0.0;
-        mag[t * mag_step] = 0.0;
     }
     Real re[K], im[K];
     while (lin < lin1) {
@@ -405,41 +395,51 @@ BBFG_FN void walk_minors_unit(const WalkArgs& A, const PermDesc& d, uint32_t u_l
         double w;
         seed<K, Real>(A, d, lane_idx, h, t0, re, im, w);
         if (!valid) w = 0.0;
-        uint32_t t = t0;
-        while (t < t1) {
-            // plain steps up to the next sampled position (one basic block per
-            // step, as without sampling), then the sampled step
-            const uint32_t run = (t1 - t < mwait) ? t1 - t : mwait;
-            const uint32_t tp = t + run;
-            for (; t < tp; ++t) {
-                if (t > t0) {
-                    const uint32_t rowi = uniform_u32(tab[t].row);
-                    kptr<Real> row = a2 + 2 * (size_t)rowi * K;
+        for (uint32_t t = t0; t < t1; ++t) {
+            if (t > t0) {
+                const uint32_t rowi = uniform_u32(tab[t].row);
+                kptr<Real> row = a2 + 2 * (size_t)rowi * K;
 #pragma unroll
-                    for (int j = 0; j < K; ++j) {
-                        re[j] += row[2 * j];
-                        im[j] += row[2 * j + 1];
-                    }
+                for (int j = 0; j < K; ++j) {
+                    re[j] += row[2 * j];
+                    im[j] += row[2 * j + 1];
                 }
-                minors_accumulate<K, G, Real>(re, im, w * tab[t].s, out_r, out_i);
             }
-            mwait -= run;
-            if (t < t1) {
-                if (t > t0) {
-                    const uint32_t rowi = uniform_u32(tab[t].row);
-                    kptr<Real> row = a2 + 2 * (size_t)rowi * K;
-#pragma unroll
-                    for (int j = 0; j < K; ++j) {
-                        re[j] += row[2 * j];
-                        im[j] += row[2 * j + 1];
-                    }
-                }
-                minors_accumulate<K, G, Real, true>(re, im, w * tab[t].s, out_r, out_i, mag, mag_step, mag_w);
-                ++t;
-                mwait = mstride - 1;
-            }
+            const double ws = w * tab[t].s;
+            minors_accumulate<K, G, Real>(re, im, ws, out_r, out_i);
         }
         lin += (uint64_t)(t1 - t0);
+    }
+#pragma unroll
+    for (int t = 0; t < G; ++t) sink.sum(t, out_r[t], out_i[t]);
+    const uint32_t every = d.mag_every;
+    if (part % every != 0) {
+#pragma unroll
+        for (int t = 0; t < G; ++t) sink.no_mag(t);
+        return;
+    }
+    // a sampled unit stands for itself and the unsampled ones after it
+    const uint32_t reps = (upg - part < every) ? upg - part : every;
+    // the column sums at the unit's last position, seeded afresh: keeping the
+    // walk's own ones alive past the loop costs the loop registers
+    const uint64_t hl = (lin1 - 1) / Q;
+    const uint32_t tl = (uint32_t)(lin1 - 1 - hl * Q);
+    double w;
+    seed<K, Real>(A, d, lane_idx, hl, tl, re, im, w);
+    if (!valid) w = 0.0;
+    double p2 = 1.0;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const double x = (double)re[j], y = (double)im[j];
+        p2 *= __builtin_fma(x, x, y * y);
+    }
+    const double wa =
+        (double)(lin1 - lin0) * (double)reps * __builtin_fabs(w * tab[tl].s) * p2 * approx_rsqrt(p2);
+#pragma unroll
+    for (int t = 0; t < G; ++t) {
+        const double x = (double)re[T + t], y = (double)im[T + t];
+        const double q = __builtin_fma(x, x, y * y);
+        sink.mag(t, q > 0.0 ? wa * approx_rsqrt(q) : 0.0);
     }
 }
 

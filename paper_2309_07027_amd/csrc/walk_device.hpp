@@ -73,4 +73,31 @@ __device__ __forceinline__ void store_partial_all_lanes(double* partials, uint64
     p[4] = a;
 }
 
+// The two halves of store_partial_all_lanes, for callers that have the sums
+// and the magnitude sum at different times: slot's (re, im) double-double sums
+// over the wavefront, then its magnitude sum.
+__device__ __forceinline__ void store_partial_sums_all_lanes(double* partials, uint64_t slot, double r, double i)
+{
+    ddv sr = {r, 0.0}, si = {i, 0.0};
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        ddv orr = {__shfl_xor(sr.hi, off), __shfl_xor(sr.lo, off)};
+        ddv oi = {__shfl_xor(si.hi, off), __shfl_xor(si.lo, off)};
+        sr = dd_add(sr, orr);
+        si = dd_add(si, oi);
+    }
+    double* p = partials + slot * kPartialDoubles;
+    p[0] = sr.hi;
+    p[1] = sr.lo;
+    p[2] = si.hi;
+    p[3] = si.lo;
+}
+
+__device__ __forceinline__ void store_partial_mag_all_lanes(double* partials, uint64_t slot, double a)
+{
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) a += __shfl_xor(a, off);
+    partials[slot * kPartialDoubles + 4] = a;
+}
+
 }  // namespace bbfg

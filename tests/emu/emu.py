@@ -17,19 +17,34 @@ CMD = ["g++", "-O1", "-g", "-std=c++17", "-ffp-contract=off", "-fsanitize=addres
 
 
 def build():
-    newest = max(p.stat().st_mtime for p in SOURCES + HEADERS)
-    if not EXE.exists() or EXE.stat().st_mtime < newest:
-        subprocess.run(CMD, check=True)
+    """Rebuilds the emulator when a source is newer.  Parallel test workers
+    serialise on a lock file, and the binary is replaced atomically, so no
+    worker runs a half-written one."""
+    import fcntl
+
+    def stale():
+        newest = max(p.stat().st_mtime for p in SOURCES + HEADERS)
+        return not EXE.exists() or EXE.stat().st_mtime < newest
+
+    if not stale():
+        return EXE
+    with open(HERE / ".walk_emu.lock", "w") as lock:
+        fcntl.flock(lock, fcntl.LOCK_EX)
+        if stale():
+            tmp = EXE.with_name(f"walk_emu.tmp{os.getpid()}")
+            subprocess.run(CMD[:-1] + [str(tmp)], check=True)
+            os.replace(tmp, EXE)
     return EXE
 
 
-def run(A, M, slots: int, f32: bool = False, l_batch: int = 0):
+def run(A, M, slots: int, f32: bool = False, l_batch: int = 0, ryser: bool = False):
     """Emulated evaluation: (value, rel_err_est, kappa, units).  l_batch = 0 plans
     the permanent as perm_bbfg does; l_batch > 0 as a batched launch with that
-    unit length."""
+    unit length.  ryser: Eq. ryser with row multiplicities on the same walk."""
     A = np.ascontiguousarray(np.asarray(A, dtype=np.complex128))
     r, n = A.shape
-    lines = [f"{r} {n} {int(slots)} {1 if f32 else 0} {int(l_batch)} 0", " ".join(str(int(m)) for m in M)]
+    lines = [f"{r} {n} {int(slots)} {1 if f32 else 0} {int(l_batch)} {3 if ryser else 0}",
+             " ".join(str(int(m)) for m in M)]
     lines.append(" ".join(f"{float(x.real).hex()} {float(x.imag).hex()}" for x in A.ravel()))
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0")
     p = subprocess.run([str(EXE)], input="\n".join(lines) + "\n", capture_output=True, text=True, env=env,

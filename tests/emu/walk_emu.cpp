@@ -13,6 +13,8 @@
 //         item as a batched launch does (fixed unit length), 0 as a single launch.
 //         minors = 1: the multiplicities sum to n - 1 and the n leave-one-column-
 //         out permanents are formed as the batched minors walk does (FP64).
+//         minors = 3: the Ryser formula (Eq. ryser with row multiplicities) on
+//         the same walk, FP64.
 //         minors = 2: column multiplicities; one more line of n column
 //         multiplicities (>= 1) follows the row multiplicities (FP64).  As the
 //         library does, equal multiplicities e >= 2 use (prod_j c_j)^e over the
@@ -75,7 +77,7 @@ void run_unit_pow(const WalkArgs& W, const PermDesc& d, uint32_t u, uint32_t lan
 // (prod_j c_j)^e (FP64 only).
 template <typename Real>
 int emulate(int n_rows, int n, long long slots, long long l_batch, const std::vector<int32_t>& M,
-            const std::vector<double>& A, const std::vector<int32_t>& N = {})
+            const std::vector<double>& A, const std::vector<int32_t>& N = {}, bool ryser = false)
 {
     const bool pow = !N.empty();
     const int n_total = pow ? n * N[0] : n;
@@ -84,6 +86,7 @@ int emulate(int n_rows, int n, long long slots, long long l_batch, const std::ve
     std::string err;
     PlanParams pp;
     pp.l_batch = (uint64_t)l_batch;
+    pp.ryser = ryser;
     int rc = build_plan(M.data(), n_rows, n_total, (uint64_t)slots, pp, P, err);
     if (rc) {
         std::fprintf(stderr, "plan error %d: %s\n", rc, err.c_str());
@@ -128,6 +131,7 @@ int emulate(int n_rows, int n, long long slots, long long l_batch, const std::ve
     d.unit_base = 0;
     d.units = P.units;
     d.units_per_group = P.units_per_group;
+    d.mag_every = mag_every_for(P.units_per_group);
     d.span = P.span;
     d.rowinfo_off = 0;
     d.n = n;
@@ -135,7 +139,7 @@ int emulate(int n_rows, int n, long long slots, long long l_batch, const std::ve
     d.Q = P.Q;
     d.lane_product = P.lane_product;
     d.groups = P.groups;
-    d.scale = std::ldexp(1.0, 1 - n_total);
+    d.scale = std::ldexp(1.0, P.scale_log2);
     d.err_coeff = P.err_coeff * (f32 ? 0x1.0p-24 : 0x1.0p-53);
     d.col_pow = pow ? (uint32_t)N[0] : 1u;
 
@@ -247,11 +251,26 @@ void butterfly(ddv* sr, ddv* si)
     }
 }
 
+// One lane's unit results: sums and magnitude sum per target.
+struct LaneSink {
+    double *r, *i, *a;
+    void sum(int t, double re, double im)
+    {
+        r[t] = re;
+        i[t] = im;
+    }
+    void mag(int t, double v) { a[t] = v; }
+    void no_mag(int t) { a[t] = 0.0; }
+};
+
 template <int KMIN, int KMAX>
 void run_minor_unit(const WalkArgs& W, const PermDesc& d, uint32_t u, uint32_t lane, double* r, double* i, double* mag)
 {
     if constexpr (KMIN <= KMAX) {
-        if (d.n == KMIN) walk_minors_unit<KMIN, minor_group(KMIN), double>(W, d, u, lane, r, i, mag, 1);
+        if (d.n == KMIN) {
+            LaneSink sink{r, i, mag};
+            walk_minors_unit<KMIN, minor_group(KMIN), double>(W, d, u, lane, sink);
+        }
         else run_minor_unit<KMIN + 1, KMAX>(W, d, u, lane, r, i, mag);
     }
 }
@@ -315,6 +334,8 @@ int emulate_minors(int n_rows, int K, long long slots, long long l_batch, const 
         d.tab = P.table->data();
         d.units = P.units;
         d.units_per_group = P.units_per_group;
+        d.mag_every = mag_every_for(P.units_per_group);
+    d.mag_every = mag_every_for(P.units_per_group);
         d.span = P.span;
         d.n = K;
         d.r = r;
@@ -324,7 +345,6 @@ int emulate_minors(int n_rows, int K, long long slots, long long l_batch, const 
         d.scale = std::ldexp(1.0, 1 - (K - 1));
         d.err_coeff = P.err_coeff * 0x1.0p-53;
         d.targets = (uint32_t)G;
-        d.mag_stride = P.n_addends > kMagExactAddends ? kMagStride : 1u;
         WalkArgs W;
         std::memset(&W, 0, sizeof W);
         W.rowinfo = P.rows.data();
@@ -419,6 +439,7 @@ int main()
         return 2;
     }
     if (minors == 1) return emulate_minors(n_rows, n, slots, l_batch, M, A);
+    if (minors == 3) return emulate<double>(n_rows, n, slots, l_batch, M, A, {}, true);
     if (minors == 2) {
         bool uniform = true;
         for (int32_t e : N) uniform = uniform && e == N[0];

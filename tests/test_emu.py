@@ -116,26 +116,25 @@ def test_minors_walk_matches_oracle(oracle, modes, Ks):
                     assert e <= TOL, (K, l, M, L, e)
 
 
-@pytest.mark.parametrize("K,M", [(14, [1] * 13), (24, [2] * 6 + [1] * 11), (36, [4] * 8 + [3])])
+@pytest.mark.parametrize("K,M", [(14, [1] * 13), (16, [1] * 15), (24, [2] * 6 + [1] * 11), (36, [4] * 8 + [3])])
 def test_minors_kappa_estimate(oracle, K, M):
-    """The walk's per-minor conditioning (magnitudes |re| + |im| of the addends,
-    taken at every Gray position up to 2^20 addends and at every 257th beyond)
-    against the oracle's sum of |addend| / |perm|.  Every position: between 1
-    and sqrt(2) times it (the 1-norm bound), up to rounding.  Sampled (K = 36
-    has C' = 3 * 5^8 > 2^20 addends): an estimate from ~4500 positions of a
-    heavy-tailed sum, within a factor of about 2 either way."""
+    """The walk's per-minor conditioning estimate against the oracle's sum of
+    |addend| / |perm|, at unit lengths 64, 512 and 4096.  The walk samples the
+    modulus of each target's addend at one position per lane (the unit's last)
+    in about 32 units per lane group, scaled by the positions they stand for:
+    an estimate of a heavy-tailed sum (a product of K - 1 moduli).  Measured
+    over these cases: between 0.15 and 5.1 times the exact value; the bar is a
+    factor of 8 either way.  The result itself stays within min(1e-10, its own
+    estimate)."""
     U = I.haar_unitary(300 + K)
     A = np.ascontiguousarray(U[:len(M)][:, :K])
-    Mp = list(M)
-    Mp[int(np.argmin(M))] -= 1
-    sampled = np.prod([m + 1 for m in Mp]) > 2 ** 20
-    got, est, kap = emu.run_minors(A, M, 512, 1, with_err=True)
-    for l in range(K):
-        ref, absum = oracle.perm_generalized(np.delete(A, l, axis=1), M, with_abs=True)
-        ratio = kap[l] / (absum / abs(ref))
-        lo, hi = (0.4, 2.5) if sampled else (1.0 - 1e-12, np.sqrt(2.0) + 1e-12)
-        assert lo <= ratio <= hi, (K, l, ratio)
-        assert rel(got[l], ref) <= min(TOL, est[l]), (K, l)
+    refs = [oracle.perm_generalized(np.delete(A, l, axis=1), M, with_abs=True) for l in range(K)]
+    for L in (64, 512, 4096):
+        got, est, kap = emu.run_minors(A, M, L, 1, with_err=True)
+        for l, (ref, absum) in enumerate(refs):
+            ratio = kap[l] / (absum / abs(ref))
+            assert 1.0 / 8.0 <= ratio <= 8.0, (K, L, l, ratio)
+            assert rel(got[l], ref) <= min(TOL, est[l]), (K, L, l)
 
 
 @pytest.mark.parametrize("seed", [31, 32])
@@ -157,3 +156,24 @@ def test_column_multiplicities_match_oracle(oracle, seed):
         for slots, L in ((1, 64), (2048, 0)):
             v, err, kappa, units = emu.run_cols(A, M, N, slots, L)
             assert rel(v, ref) <= TOL, (n, M.tolist(), N.tolist(), slots, L)
+
+
+@pytest.mark.parametrize("kind", ["distinct", "bunched"])
+def test_ryser_walk_matches_oracle(oracle, kind):
+    """The walk planned for Eq. ryser (no pivot row, base coefficient 0, scale
+    2^-n) against the oracle's generalized Ryser and its BB/FG value, single and
+    batched splits; its error estimate covers its error."""
+    rng = np.random.default_rng({"distinct": 41, "bunched": 42}[kind])
+    for n in (1, 2, 3, 6, 11, 15):
+        if kind == "distinct":
+            A, M = I.random_instance(rng, n, distinct=True)
+        else:
+            A, M = I.random_instance(rng, n, m=max(2, n // 2))
+        ref_r = oracle.perm_ryser_generalized(A, M)
+        ref = oracle.perm_generalized(A, M)
+        for slots, L in ((512, 0), (1, 64)):
+            v, err, kappa, units = emu.run(A, M, slots, l_batch=L, ryser=True)
+            e = rel(v, ref)
+            assert e <= max(err, 1e-15), (n, M, slots, e, err)
+            assert rel(v, ref_r) <= max(err, 1e-15)
+            assert e <= 1e-8, (n, e)

@@ -553,3 +553,51 @@ def test_c3_batch_after_autotuning_vs_golden():
     say(f"  fp64 max {e64.max():.2e}; fp32 median {np.median(e32):.2e} max {e32.max():.2e}")
     assert (e64 <= TOL).all(), np.nonzero(e64 > TOL)[0][:10]
     assert (e32 <= err32).all(), np.nonzero(e32 > err32)[0][:10]
+
+
+# ---------------------------------------------------------------------------
+# Eq. (ryser) with row multiplicities on the same walk (Sec. 3.2 comparison)
+# ---------------------------------------------------------------------------
+
+def test_ryser_vs_oracle_and_emulation(oracle):
+    """perm_ryser against the oracle (its generalized Ryser and the BB/FG value)
+    within its own error estimate, and bit for bit against the CPU emulation of
+    the same plan; the batched Ryser path equals the single one to the
+    estimate."""
+    from tests.emu import emu
+    emu.build()
+    rng = np.random.default_rng(707)
+    mats = []
+    for n, kind in ((1, "random"), (4, "bunched"), (9, "distinct"), (13, "bunched"), (16, "random"),
+                    (20, "distinct")):
+        A, M = rand_instance(rng, n, kind)
+        say(f"case ryser n={n} M={M.tolist()}")
+        v, info = B.perm_ryser(A, M, with_info=True)
+        ref = oracle.perm_generalized(A, M)
+        assert rel(v, ref) <= max(info["rel_err_est"], 1e-15), (n, rel(v, ref), info["rel_err_est"])
+        if n <= 13:
+            assert rel(v, oracle.perm_ryser_generalized(A, M)) <= max(info["rel_err_est"], 1e-15)
+        waves, ncu = B.walk_occupancy(n)
+        e, *_ = emu.run(A, M, waves * ncu, ryser=True)
+        assert v == e, (n, v, e)
+        assert info["n_addends"] == int(np.prod(np.asarray(M) + 1))
+        mats.append((A, M))
+    vb, eb = B.perm_batch(mats, precision=B.BBFG_RYSER, with_err=True)
+    for (A, M), g, e in zip(mats, vb, eb):
+        assert rel(g, B.perm_ryser(A, M)) <= 2 * max(e, 1e-15)
+
+
+def test_ryser_c2_accuracy_vs_bbfg(golden):
+    """The comparison of Sec. 3.2 at n = 30: both engines (same walk, FP64)
+    against the stored oracle values; Ryser's error within its estimate, and
+    its conditioning (kappa) larger than BB/FG's."""
+    for case in ("c2a", "c2b", "c2c"):
+        A, M, ref, _ = golden[case]
+        say(f"case ryser accuracy {case}")
+        vb, ib = B.perm_bbfg(A, M, with_info=True)
+        vr, ir = B.perm_ryser(A, M, with_info=True)
+        eb, er = rel(vb, ref), rel(vr, ref)
+        say(f"  {case}: bbfg err {eb:.2e} (kappa {ib['kappa']:.1e}), ryser err {er:.2e} (kappa {ir['kappa']:.1e})")
+        assert eb <= TOL
+        assert er <= ir["rel_err_est"]
+        assert ir["kappa"] > ib["kappa"]
