@@ -7,7 +7,8 @@
 // tuned per n: a synthetic batch of n-photon permanents (photons placed at
 // random on 60 modes, as in the sampling workloads) is timed for each
 // candidate L and, among those within 2 % of the fastest per addend, the
-// longest is kept (the shortest for the minors kind).  Untuned n use a default.
+// longest is kept (the shortest for the minors kind); the plain kinds' picks are
+// then made non-increasing in n.  Untuned n use a default.
 // Each candidate's timed launch of the plain kinds holds about 2^28 addends (at
 // most 16384 items, distinct matrices repeated; milliseconds at large n,
 // against tens of microseconds of launch noise).  Each candidate's rate comes
@@ -162,6 +163,16 @@ try {
         ++c->plan_epoch;
         dA.release();
     }
+    // Plain kinds: a unit's duration grows with n at a fixed L while its fixed
+    // costs do not, so the best L does not grow with n.  Picks within 2 % of the
+    // best rate are flat optima, so the tuned lengths are made non-increasing in n
+    // over the tuned range (the shorter of two near-equal picks).
+    if (!minors)
+        for (int n = n_lo + 1; n <= n_hi; ++n) {
+            uint64_t& L = c->batch_L[std::make_pair(n, kind)];
+            L = std::min(L, c->batch_L[std::make_pair(n - 1, kind)]);
+        }
+    ++c->plan_epoch;
     if (cache_path) {
         FILE* f = std::fopen(cache_path, "w");
         if (!f) return set_error(BBFG_EINVAL, "cannot write %s", cache_path);

@@ -64,6 +64,13 @@ struct HostPlan {
     int scale_log2 = 0;            // the walk's sum times 2^scale_log2 is the permanent
     std::vector<uint32_t> low_radix;  // radices of the low digits (table key)
     TablePtr table;                // Q entries
+    // scratch of one evaluation (run_perms, under the context's lock): the
+    // evaluation that last placed this plan's row records, their offset and the
+    // device copy of its table, so items sharing the plan find them without a
+    // lookup
+    mutable uint64_t slot_call = 0;
+    mutable size_t slot_rowinfo = 0;
+    mutable const TabEntry* slot_table = nullptr;
 };
 
 // Plans perm(A, M) for the n_rows multiplicities `mult` (sum == n_cols), for a

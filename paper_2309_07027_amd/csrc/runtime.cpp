@@ -2,6 +2,7 @@
 #include "runtime.hpp"
 
 #include <algorithm>
+#include <atomic>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -347,8 +348,11 @@ int run_perms(Context& c, Workspace& w, std::vector<PermItem>& items, int f32, b
     auto stride_of = [](const PermItem& it) { return (uint64_t)(it.targets > 0 ? it.targets : 1); };
 
     // distinct plans (row records are shared between equal shapes; Gray tables
-    // are resident on the device and shared between equal low radices)
-    std::unordered_map<const HostPlan*, std::pair<size_t, const TabEntry*>> plan_slot;  // -> (rowinfo off, table)
+    // are resident on the device and shared between equal low radices); each
+    // plan records its slot for this evaluation in its slot_* fields
+    static std::atomic<uint64_t> evaluations{0};
+    const uint64_t call = ++evaluations;
+    std::vector<const HostPlan*> distinct;
     size_t n_rowinfo = 0, n_srcrow = 0, n_srccol = 0;
     struct Upload {
         const HostPlan* plan;
@@ -363,7 +367,7 @@ int run_perms(Context& c, Workspace& w, std::vector<PermItem>& items, int f32, b
     int nmax = 0;
     for (auto& it : items) {
         const HostPlan* p = it.plan.get();
-        if (plan_slot.find(p) == plan_slot.end()) {
+        if (p->slot_call != call) {
             auto te = c.dev_tables.find(p->table.get());
             auto up = uploading.find(p->table.get());
             const TabEntry* dt = nullptr;
@@ -386,7 +390,10 @@ int run_perms(Context& c, Workspace& w, std::vector<PermItem>& items, int f32, b
                 upload_bytes += (bytes + 255) / 256 * 256;
                 dt = dst;
             }
-            plan_slot[p] = {n_rowinfo, dt};
+            p->slot_call = call;
+            p->slot_rowinfo = n_rowinfo;
+            p->slot_table = dt;
+            distinct.push_back(p);
             n_rowinfo += (size_t)p->r;
         }
         const int nc = cols_of(it);
@@ -449,26 +456,24 @@ int run_perms(Context& c, Workspace& w, std::vector<PermItem>& items, int f32, b
     uint32_t* hs = reinterpret_cast<uint32_t*>(H + off_src);
     uint32_t* hc = reinterpret_cast<uint32_t*>(H + off_col);
     uint32_t* hri = reinterpret_cast<uint32_t*>(H + off_ritem);
-    for (const auto& kv : plan_slot)
-        std::memcpy(hr + kv.second.first, kv.first->rows.data(), sizeof(RowInfo) * (size_t)kv.first->r);
+    for (const HostPlan* p : distinct) std::memcpy(hr + p->slot_rowinfo, p->rows.data(), sizeof(RowInfo) * (size_t)p->r);
     for (const Upload& u : uploads) std::memcpy(H + off_tabs + u.off, u.plan->table->data(), u.bytes);
     uint64_t a_cursor = 0;
     size_t s_cursor = 0, c_cursor = 0;
     for (size_t i = 0; i < nitem; ++i) {
         const HostPlan& p = *items[i].plan;
-        const auto sl = plan_slot[&p];
         const int nc = cols_of(items[i]);
         PermDesc& d = hd[i];
         std::memset(&d, 0, sizeof d);
         d.a_off = a_cursor;
         d.a2_off = a_cursor + (uint64_t)p.r * nc;
         a_cursor += (uint64_t)p.r * nc * 3u;
-        d.tab = sl.second;
+        d.tab = p.slot_table;
         d.unit_base = unit_base[i];
         d.units = p.units;
         d.units_per_group = p.units_per_group;
         d.span = p.span;
-        d.rowinfo_off = (uint32_t)sl.first;
+        d.rowinfo_off = (uint32_t)p.slot_rowinfo;
         d.n = nc;
         d.r = p.r;
         d.Q = p.Q;

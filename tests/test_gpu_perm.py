@@ -221,6 +221,8 @@ def test_autotune_roundtrip(tmp_path):
     assert len(lines) >= 9
     for n in (8, 9, 10):
         assert B.batch_unit_length(n) in (64, 128, 256, 512, 1024, 2048, 4096)
+    # plain kinds: tuned lengths do not grow with n over the tuned range
+    assert B.batch_unit_length(8) >= B.batch_unit_length(9) >= B.batch_unit_length(10)
     B.autotune_load(str(path))
     mats = [I.c3_item(i) for i in range(16)]
     got = B.perm_batch(mats)
