@@ -244,9 +244,10 @@ int perm_bbfg_cols(const bbfg_c128 *A, int32_t n_rows, const int32_t *row_mult, 
  *   rel_err_est  nullable, n_cols doubles (host): estimated relative error of
  *             out[l], kappa_l * u * (n + sqrt(Q)) with kappa_l the sum of
  *             |addend| of minor l over |out[l]|.  The sum of |addend| is
- *             estimated from one sample per lane and work unit (the addend's
- *             modulus at the unit's last position times the unit's length):
- *             within a factor of 8 of the exact kappa_l in the cases tested.
+ *             estimated from one sample per lane in about 32 work units per
+ *             group of 64 lanes (the addend's modulus at the unit's last
+ *             position times the positions it stands for): within a factor of
+ *             8 of the exact kappa_l in the cases tested.
  *
  * FP64 with double-double reduction.  n_cols = 1 gives the empty permanent 1.
  * The walk is split to fill the device (as perm_bbfg splits a lone permanent),

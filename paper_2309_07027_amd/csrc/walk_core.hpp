@@ -28,17 +28,10 @@ BBFG_FN kptr<T> kconst(const T* p)
     return (kptr<T>)p;
 }
 BBFG_FN uint32_t uniform_u32(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
-// 1/sqrt(x) from the hardware's approximate reciprocal square root (for
-// estimates only)
-BBFG_FN double approx_rsqrt(double x) { return __builtin_amdgcn_rsq(x); }
 }  // namespace bbfg
 #else
 #define BBFG_FN inline
 #include "emu_ptr.hpp"
-#include <cmath>
-namespace bbfg {
-inline double approx_rsqrt(double x) { return 1.0 / std::sqrt(x); }
-}  // namespace bbfg
 #endif
 
 namespace bbfg {
@@ -352,14 +345,12 @@ BBFG_FN void minors_accumulate(const Real* re, const Real* im, double ws, double
 // sink.mag(t, a_t) with the lane's estimate of the sum of |addend| of target t
 // over its positions in this unit and the d.mag_every - 1 units after it: the
 // modulus of the addend at the unit's last position,
-//   |w s| prod_{j != K-G+t} |c_j| = |w s| sqrt(P2) / |c_{K-G+t}|,
-// P2 the product of all K squared moduli, times the unit's number of
-// positions and the number of units it stands for (one sample per lane, from
-// column sums seeded afresh at that position, so the walk loop carries no
-// extra work or registers; the reciprocal square roots are the hardware's
-// approximation); the other units call sink.no_mag(t).  a_t is 0 where target
-// t's own column sum is exactly zero.  The passes over the targets are
-// separate loops, each small enough to be unrolled in full.
+//   |w s| prod_{j != K-G+t} |c_j|,
+// times the unit's number of positions and the number of units it stands for
+// (one sample per lane, from column sums seeded afresh at that position, so
+// the walk loop carries no extra work or registers); the other units call
+// sink.no_mag(t).  The passes over the targets are separate loops, each small
+// enough to be unrolled in full.
 template <int K, int G, typename Real, typename Sink>
 BBFG_FN void walk_minors_unit(const WalkArgs& A, const PermDesc& d, uint32_t u_local, uint32_t lane, Sink& sink)
 {
@@ -427,19 +418,25 @@ BBFG_FN void walk_minors_unit(const WalkArgs& A, const PermDesc& d, uint32_t u_l
     double w;
     seed<K, Real>(A, d, lane_idx, hl, tl, re, im, w);
     if (!valid) w = 0.0;
-    double p2 = 1.0;
+    // moduli |c_j| in re[] (im[] is free after this), then each target's
+    // leave-one-out product of moduli from prefix products (kept in im[]) and a
+    // running suffix product: no division, so zero column sums are harmless
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         const double x = (double)re[j], y = (double)im[j];
-        p2 *= __builtin_fma(x, x, y * y);
+        re[j] = (Real)__builtin_sqrt(__builtin_fma(x, x, y * y));
     }
-    const double wa =
-        (double)(lin1 - lin0) * (double)reps * __builtin_fabs(w * tab[tl].s) * p2 * approx_rsqrt(p2);
+    double lead = (double)(lin1 - lin0) * (double)reps * __builtin_fabs(w * tab[tl].s);
 #pragma unroll
-    for (int t = 0; t < G; ++t) {
-        const double x = (double)re[T + t], y = (double)im[T + t];
-        const double q = __builtin_fma(x, x, y * y);
-        sink.mag(t, q > 0.0 ? wa * approx_rsqrt(q) : 0.0);
+    for (int j = 0; j < T; ++j) lead *= (double)re[j];
+    im[T] = (Real)lead;
+#pragma unroll
+    for (int t = 1; t < G; ++t) im[T + t] = (Real)((double)im[T + t - 1] * (double)re[T + t - 1]);
+    double suffix = 1.0;
+#pragma unroll
+    for (int t = G - 1; t >= 0; --t) {
+        sink.mag(t, (double)im[T + t] * suffix);
+        suffix *= (double)re[T + t];
     }
 }
 

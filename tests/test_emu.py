@@ -137,6 +137,29 @@ def test_minors_kappa_estimate(oracle, K, M):
             assert rel(got[l], ref) <= min(TOL, est[l]), (K, L, l)
 
 
+@pytest.mark.parametrize("K", [12, 26])
+def test_minors_estimate_with_a_zero_column(oracle, K):
+    """A zero column makes its column sum zero at every Gray position.  Every
+    other minor keeps that column, so it is 0 with an infinite estimate; the
+    minor that drops it is a generic permanent whose estimate must come from
+    the other columns' moduli (a leave-one-out product, no division by the
+    zero modulus): finite, positive and covering its error."""
+    rng = np.random.default_rng(900 + K)
+    A, M = _minor_case(rng, K, 60)
+    z = K // 3
+    A = A.copy()
+    A[:, z] = 0.0
+    for L in (64, 512):
+        got, est, _ = emu.run_minors(A, M, L, 1, with_err=True)
+        ref = oracle.perm_generalized(np.delete(A, z, axis=1), M)
+        e = rel(got[z], ref)
+        assert np.isfinite(est[z]) and 0.0 < est[z] < 1e-8, (K, L, est[z])
+        assert e <= min(TOL, est[z]), (K, L, e, est[z])
+        for l in range(K):
+            if l != z:
+                assert got[l] == 0, (K, L, l, got[l])
+
+
 @pytest.mark.parametrize("seed", [31, 32])
 def test_column_multiplicities_match_oracle(oracle, seed):
     """Column multiplicities (Eq. bbfgrepeated) against the oracle's permanent of
