@@ -8,7 +8,8 @@
 // random on 60 modes, as in the sampling workloads) is timed for each
 // candidate L and, among those within 2 % of the fastest per addend, the
 // longest is kept (the shortest for the minors kind); the plain kinds' picks are
-// then made non-increasing in n.  Untuned n use a default.
+// then made non-increasing in n, the minors' picks median-filtered over n.
+// Untuned n use a default.
 // Each candidate's timed launch of the plain kinds holds about 2^28 addends (at
 // most 16384 items, distinct matrices repeated; milliseconds at large n,
 // against tens of microseconds of launch noise).  Each candidate's rate comes
@@ -167,11 +168,23 @@ try {
     // costs do not, so the best L does not grow with n.  Picks within 2 % of the
     // best rate are flat optima, so the tuned lengths are made non-increasing in n
     // over the tuned range (the shorter of two near-equal picks).
-    if (!minors)
+    // The minors kind keeps the shortest pick within 2 %, which jumps where the
+    // rate is flat over several lengths (1024 at one n between 256s): each pick is
+    // replaced by the median of itself and its tuned neighbours.
+    if (!minors) {
         for (int n = n_lo + 1; n <= n_hi; ++n) {
             uint64_t& L = c->batch_L[std::make_pair(n, kind)];
             L = std::min(L, c->batch_L[std::make_pair(n - 1, kind)]);
         }
+    } else if (n_hi - n_lo >= 2) {
+        std::vector<uint64_t> picks;
+        for (int n = n_lo; n <= n_hi; ++n) picks.push_back(c->batch_L[std::make_pair(n, kind)]);
+        for (int n = n_lo + 1; n < n_hi; ++n) {
+            uint64_t w[3] = {picks[(size_t)(n - 1 - n_lo)], picks[(size_t)(n - n_lo)], picks[(size_t)(n + 1 - n_lo)]};
+            std::sort(w, w + 3);
+            c->batch_L[std::make_pair(n, kind)] = w[1];
+        }
+    }
     ++c->plan_epoch;
     if (cache_path) {
         FILE* f = std::fopen(cache_path, "w");

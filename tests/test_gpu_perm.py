@@ -418,6 +418,30 @@ def test_minors_errors():
     assert B.perm_minors(np.ones((1, 1), dtype=np.complex128), [0])[0] == 1
 
 
+@pytest.mark.parametrize("K", [12, 26, 34])
+def test_minors_estimate_with_a_zero_column(oracle, K):
+    """A zero column: every minor that keeps it is exactly 0 (its estimate is
+    infinite), and the minor that drops it gets a finite, positive estimate
+    from the other columns' moduli that covers its error (GPU split, several
+    buckets)."""
+    rng = np.random.default_rng(910 + K)
+    u = I.haar_from_rng(rng, 60)
+    modes = 60 if K <= 26 else 6  # heavy bunching keeps the oracle's sum short at K = 34
+    kept, M = I.bunch(rng.integers(0, modes, K - 1), 60)
+    A = np.ascontiguousarray(u[kept][:, :K])
+    z = K // 3
+    A[:, z] = 0.0
+    say(f"case minors zero column K={K}")
+    got, est = B.perm_minors(A, M, with_err=True)
+    ref = oracle.perm_generalized(np.delete(A, z, axis=1), M)
+    e = rel(got[z], ref)
+    assert np.isfinite(est[z]) and 0.0 < est[z] < 1e-8, (K, est[z])
+    assert e <= min(TOL, est[z]), (K, e, est[z])
+    for l in range(K):
+        if l != z:
+            assert got[l] == 0, (K, l, got[l])
+
+
 def test_results_independent_of_cache_flushes():
     """Plans, Gray tables and captured graphs are dropped and rebuilt when the
     caches fill.  Tiny bounds force that many times per call, also while a batch
