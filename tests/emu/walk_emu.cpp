@@ -335,7 +335,6 @@ int emulate_minors(int n_rows, int K, long long slots, long long l_batch, const 
         d.units = P.units;
         d.units_per_group = P.units_per_group;
         d.mag_every = mag_every_for(P.units_per_group);
-    d.mag_every = mag_every_for(P.units_per_group);
         d.span = P.span;
         d.n = K;
         d.r = r;
