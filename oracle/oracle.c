@@ -787,8 +787,23 @@ static int draw_index(int rows, const double *w, double u)
  * input occupation (rows x n), every one of the `rows` rows a candidate
  * output mode, the occupation of the first m rows reported.  Random numbers
  * as described above. */
+static int cc_sample_rows_kept(int rows, int m, const double *src, int ld, const int *input_occ, int n,
+                               int n_samples, uint64_t seed, double keep, int *out_occ);
+
 static int cc_sample_rows(int rows, int m, const double *src, int ld, const int *input_occ, int n,
                           int n_samples, uint64_t seed, int *out_occ)
+{
+    return cc_sample_rows_kept(rows, m, src, ld, input_occ, n, n_samples, seed, 1.0, out_occ);
+}
+
+/* As cc_sample_rows, with the uniform part of the loss taken out at the input
+ * (Sec. 4): before its steps, sample s keeps each input photon b (the b-th
+ * column in input order) with probability `keep`, using draw 2n-1+b of its key
+ * (u = (x >> 11) 2^-53, kept when u < keep); the kept photons, in the order pi
+ * gives them, are its columns, and it draws one output row per kept photon.
+ * keep = 1 draws nothing extra and is the ideal sampler. */
+static int cc_sample_rows_kept(int rows, int m, const double *src, int ld, const int *input_occ, int n,
+                               int n_samples, uint64_t seed, double keep, int *out_occ)
 {
     double *A = (double *)malloc(sizeof(double) * 2 * (size_t)rows * (size_t)(n > 0 ? n : 1));
     double *w = (double *)malloc(sizeof(double) * (size_t)rows);
@@ -810,7 +825,18 @@ static int cc_sample_rows(int rows, int m, const double *src, int ld, const int 
             int j = (int)(((x >> 32) * (uint64_t)(i + 1)) >> 32);
             int t = pi[i]; pi[i] = pi[j]; pi[j] = t;
         }
-        for (int k = 1; k <= n; ++k) {
+        int steps = n;
+        if (keep < 1.0) {
+            int alive[64], kept[64];
+            for (int b = 0; b < n; ++b) {
+                uint64_t x = sm64_draw(key, (uint64_t)(2 * n - 1 + b));
+                alive[b] = (double)(x >> 11) * 0x1.0p-53 < keep;
+            }
+            steps = 0;
+            for (int l = 0; l < n; ++l) if (alive[pi[l]]) kept[steps++] = pi[l];
+            for (int l = 0; l < steps; ++l) pi[l] = kept[l];
+        }
+        for (int k = 1; k <= steps; ++k) {
             rc = cc_weights(rows, n, A, prefix, k, pi, w);
             if (rc) break;
             uint64_t x = sm64_draw(key, (uint64_t)(n - 1 + (k - 1)));
@@ -819,7 +845,7 @@ static int cc_sample_rows(int rows, int m, const double *src, int ld, const int 
         }
         int *o = out_occ + (size_t)s * (size_t)m;
         for (int i = 0; i < m; ++i) o[i] = 0;
-        for (int k = 0; k < n; ++k) if (prefix[k] < m) o[prefix[k]]++;
+        for (int k = 0; k < steps; ++k) if (prefix[k] < m) o[prefix[k]]++;
     }
     free(A); free(w);
     return rc;
@@ -849,6 +875,21 @@ int oracle_cc_sample(int m, const double *U, const int *input_occ, int n_samples
 }
 
 /* ------------------------------------------------------------------------- */
+/* Uniform loss taken out of the interferometer (Sec. 4): a loss that acts   */
+/* alike on every mode commutes with U, so it can be applied as a pure-loss  */
+/* channel on the input photons before an ideal simulation with U: each     */
+/* photon survives with probability 1 - loss, and the survivors are sampled  */
+/* on the m modes of U (no doubled modes).  Same law as oracle_cc_sample     */
+/* with the same loss; other random numbers.                                 */
+int oracle_cc_sample_extracted(int m, const double *U, const int *input_occ, int n_samples,
+                               double loss, uint64_t seed, int *out_occ)
+{
+    if (m < 1 || m > 128 || n_samples < 0 || !(loss >= 0.0 && loss < 1.0)) return -1;
+    int n = count_photons(m, input_occ);
+    if (n < 0 || n > 24) return -1;
+    return cc_sample_rows_kept(m, m, U, m, input_occ, n, n_samples, seed, 1.0 - loss, out_occ);
+}
+
 /* Non-uniform loss (Sec. 4): a lossy interferometer is described by a       */
 /* matrix T that is no longer unitary, a contraction (T^H T <= I).  With     */
 /* the photons entering the first m of 2m modes, the sampled law depends     */

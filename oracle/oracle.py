@@ -71,6 +71,8 @@ def lib():
         L.oracle_perm_ryser_generalized.argtypes = [ctypes.c_int, ctypes.c_int, _D, _I, _D, _D]
         L.oracle_contraction_isometry.argtypes = [ctypes.c_int, _D, _D]
         L.oracle_cc_sample_lossy.argtypes = [ctypes.c_int, _D, _I, ctypes.c_int, ctypes.c_uint64, _I]
+        L.oracle_cc_sample_extracted.argtypes = [ctypes.c_int, _D, _I, ctypes.c_int, ctypes.c_double,
+                                                 ctypes.c_uint64, _I]
         _lib = L
     return _lib
 
@@ -268,6 +270,21 @@ def cc_sample(U, input_occ, n_samples: int, loss: float, seed: int) -> np.ndarra
                                 ctypes.c_uint64(seed & (2**64 - 1)), _ip(out))
     if rc:
         raise ValueError(f"oracle_cc_sample rc={rc}")
+    return out
+
+
+def cc_sample_extracted(U, input_occ, n_samples: int, loss: float, seed: int) -> np.ndarray:
+    """Clifford & Clifford samples with the uniform loss taken out at the input
+    (Sec. 4): each photon survives with probability 1 - loss, the survivors are
+    sampled on the m modes of U (n_samples x m occupations)."""
+    U = _cmat(U)
+    m = U.shape[0]
+    occ = _ivec(input_occ)
+    out = np.zeros((n_samples, m), dtype=np.int32)
+    rc = lib().oracle_cc_sample_extracted(m, _dp(U), _ip(occ), int(n_samples), float(loss),
+                                          ctypes.c_uint64(seed & (2**64 - 1)), _ip(out))
+    if rc:
+        raise ValueError(f"oracle_cc_sample_extracted rc={rc}")
     return out
 
 

@@ -463,6 +463,50 @@ def test_dilation_is_unitary_and_marginal_matches_loss_then_u(oracle):
             assert abs(dil - cf) < 1e-14
 
 
+def _loss_then_u_law(oracle, U, S, eta, T):
+    # closed form: each input photon survives independently with probability
+    # eta, then the survivors pass U (Eq. bs_p)
+    m, n = len(S), sum(S)
+    idx = [i for i in range(m) for _ in range(S[i])]
+    p = 0.0
+    for surv in product([0, 1], repeat=n):
+        if sum(surv) != sum(T):
+            continue
+        Ss = [0] * m
+        for s_, i in zip(surv, idx):
+            Ss[i] += s_
+        p += eta ** sum(surv) * (1 - eta) ** (n - sum(surv)) * oracle.bs_prob(U, Ss, T)
+    return p
+
+
+def test_extracted_loss_sampler_law(oracle):
+    # Sec. 4: the uniform part of the loss taken out at the input (survivors
+    # sampled on U's m modes) has the law of "loss, then U" -- the same law as
+    # the doubled-mode sampler
+    from paper_2309_07027_amd.inputs import haar_unitary
+    m, eta = 4, 0.6
+    U = haar_unitary(46, m)
+    occ = [1, 1, 1, 0]
+    N = 20000
+    samples = oracle.cc_sample_extracted(U, occ, N, 1 - eta, 322)
+    counts = {}
+    for s in samples:
+        counts[tuple(s)] = counts.get(tuple(s), 0) + 1
+    tv = 0.0
+    for kept in range(4):
+        for T in patterns(m, kept):
+            tv += abs(counts.get(T, 0) / N - _loss_then_u_law(oracle, U, occ, eta, T))
+    assert 0.5 * tv < 0.03
+    assert abs(samples.sum(axis=1).mean() - 3 * eta) < 4 * math.sqrt(3 * eta * (1 - eta) / N)
+
+
+def test_extracted_loss_sampler_without_loss_is_the_ideal_sampler(oracle):
+    from paper_2309_07027_amd.inputs import haar_unitary
+    U = haar_unitary(47, 6)
+    occ = [1, 0, 2, 1, 0, 0]
+    assert np.array_equal(oracle.cc_sample_extracted(U, occ, 50, 0.0, 9), oracle.cc_sample(U, occ, 50, 0.0, 9))
+
+
 def test_splitmix64_reference_values(oracle):
     # Published SplitMix64 outputs for seed 1234567 (first five values of the generator).
     expect = [6457827717110365317, 3203168211198807973, 9817491932198370423,
