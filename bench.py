@@ -308,6 +308,16 @@ def large_sampling_section(B, I, samples_ideal: int, samples_lossy: int):
             if walk_s > 0 else None,
             "err_est_max_per_sample": float(f"{info['rel_err_est']:.3g}"),
             "photons_out": s.sum(axis=1).tolist()}
+    # the same loss taken out at the input (Sec. 4): survivors sampled on U's 60 modes
+    U, occ, loss = I.c5(True)
+    B.bs_sample_extracted(U, occ, 1, loss, 1)
+    t = time.perf_counter()
+    s, info = B.bs_sample_extracted(U, occ, samples_ideal, loss, 5, with_info=True)
+    dt = time.perf_counter() - t
+    out["lossy_0.5_extracted"] = {"samples": samples_ideal, "s_per_sample": round(dt / samples_ideal, 5),
+                                  "walk_ms": round(info["kernel_ms"], 1),
+                                  "err_est_max_per_sample": float(f"{info['rel_err_est']:.3g}"),
+                                  "photons_out_mean": round(float(s.sum(axis=1).mean()), 2)}
     return out
 
 

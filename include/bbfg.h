@@ -346,6 +346,28 @@ int bs_sample(const bbfg_c128 *U, int32_t m, const int32_t *input_occupation, in
 int bs_sample_lossy(const bbfg_c128 *T, int32_t m, const int32_t *input_occupation, int32_t n_samples,
                     uint64_t seed, int32_t *out_occupation, bbfg_info *info);
 
+/*
+ * bs_sample_extracted -- boson sampling with uniform loss taken out of the
+ * interferometer (Sec. 4: a loss that acts alike on every mode commutes with
+ * U, so it can be applied as a pure-loss channel on the input photons, and
+ * the simulation then runs on fewer photons and on U's own m modes instead of
+ * 2m).  Each input photon survives with probability 1 - loss; the survivors
+ * are sampled by Clifford & Clifford with U.  Same law as bs_sample with the
+ * same loss, not the same samples; orders of magnitude cheaper at large loss.
+ *
+ *   U, m, input_occupation, n_samples, loss, seed, out_occupation, info
+ *                     as bs_sample (loss in [0, 1); loss = 0 gives exactly the
+ *                     samples of bs_sample with loss 0).
+ *
+ * Random numbers: those of bs_sample, plus draw 2n-1+b of each sample's key
+ * deciding whether input photon b (the b-th column in input order) survives
+ * (u = (x >> 11) 2^-53 < 1 - loss); the survivors keep the sample's column
+ * order and take one step each.
+ * Errors: as bs_sample.
+ */
+int bs_sample_extracted(const bbfg_c128 *U, int32_t m, const int32_t *input_occupation, int32_t n_samples,
+                        double loss, uint64_t seed, int32_t *out_occupation, bbfg_info *info);
+
 /* ---------------------------------------------------------------------------
  * Sampling server: continuous batching of Clifford & Clifford jobs.  Sec. 4
  * scales the sampler by running independent samplers side by side (one MPI

@@ -93,6 +93,8 @@ SIGNATURES = {
     "bs_sample": (ctypes.c_int, [_P, _I32, _PI32, _I32, ctypes.c_double, ctypes.c_uint64, _PI32,
                                  ctypes.POINTER(Info)]),
     "bs_sample_lossy": (ctypes.c_int, [_P, _I32, _PI32, _I32, ctypes.c_uint64, _PI32, ctypes.POINTER(Info)]),
+    "bs_sample_extracted": (ctypes.c_int, [_P, _I32, _PI32, _I32, ctypes.c_double, ctypes.c_uint64, _PI32,
+                                           ctypes.POINTER(Info)]),
     "bs_server_create": (ctypes.c_int, [ctypes.c_size_t, _I32, ctypes.POINTER(_P)]),
     "bs_server_submit": (ctypes.c_int, [_P, _P, _I32, _PI32, _I32, ctypes.c_double, ctypes.c_uint64,
                                         ctypes.POINTER(ctypes.c_uint64)]),
@@ -330,6 +332,21 @@ def bs_sample_lossy(T, input_occupation, n_samples: int, seed: int = 0, with_inf
     info = Info()
     _check(lib().bs_sample_lossy(ptr, m, po, int(n_samples), ctypes.c_uint64(seed & (2**64 - 1)),
                                  out.ctypes.data_as(_PI32), ctypes.byref(info)))
+    del keep
+    return (out, info.as_dict()) if with_info else out
+
+
+def bs_sample_extracted(U, input_occupation, n_samples: int, loss: float = 0.0, seed: int = 0,
+                        with_info: bool = False):
+    """Samples with the uniform loss applied to the input photons (survivors
+    sampled on U's m modes): (n_samples, m) int32."""
+    ptr, keep, shape = _cmat_ptr(U)
+    m = shape[0]
+    occ, po = _i32(input_occupation)
+    out = np.zeros((n_samples, m), dtype=np.int32)
+    info = Info()
+    _check(lib().bs_sample_extracted(ptr, m, po, int(n_samples), float(loss), ctypes.c_uint64(seed & (2**64 - 1)),
+                                     out.ctypes.data_as(_PI32), ctypes.byref(info)))
     del keep
     return (out, info.as_dict()) if with_info else out
 

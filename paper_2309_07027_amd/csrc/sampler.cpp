@@ -14,6 +14,10 @@
 //   key_s = draw(seed, s); draws 0..n-2 run Fisher-Yates for i = n-1 .. 1
 //   (draw n-1-i, j = ((x >> 32) * (i + 1)) >> 32); draw n-1+(k-1) gives the
 //   uniform u = (x >> 11) * 2^-53 of step k.
+// Uniform loss taken out at the input (Sec. 4, bs_sample_extracted): a loss
+// that acts alike on every mode commutes with U, so each input photon b (the
+// b-th column) is kept when draw 2n-1+b gives u < 1 - loss; the kept columns,
+// in pi's order, are the sample's columns, one step each, on U's m modes.
 #include "sampler.hpp"
 
 #include <algorithm>
@@ -67,6 +71,7 @@ int cc_job_init(Context& c, CCJob& job, const double* U, bool U_on_device, int m
     hipStream_t s = current_stream();
     job.m = m;
     job.loss = loss;
+    job.keep = 1.0;
     job.rows = loss > 0.0 ? 2 * m : m;
     job.seed = seed;
     job.n_samples = n_samples;
@@ -151,6 +156,7 @@ int cc_job_init_matrix(Context& c, CCJob& job, const double* A_host, int rows, i
     hipStream_t s = current_stream();
     job.m = m;
     job.loss = 0.0;
+    job.keep = 1.0;
     job.rows = rows;
     job.seed = seed;
     job.n_samples = n_samples;
@@ -190,6 +196,19 @@ void cc_start_sample(CCJob& job, int s)
         const uint64_t x = splitmix64_draw(S.key, (uint64_t)(job.n - 1 - i));
         const int j = (int)(((x >> 32) * (uint64_t)(i + 1)) >> 32);
         std::swap(S.pi[(size_t)i], S.pi[(size_t)j]);
+    }
+    S.steps = job.n;
+    if (job.keep < 1.0) {
+        std::vector<char> alive((size_t)job.n);
+        for (int b = 0; b < job.n; ++b) {
+            const uint64_t x = splitmix64_draw(S.key, (uint64_t)(2 * job.n - 1 + b));
+            alive[(size_t)b] = (double)(x >> 11) * 0x1.0p-53 < job.keep;
+        }
+        int kept = 0;
+        for (int l = 0; l < job.n; ++l)
+            if (alive[(size_t)S.pi[(size_t)l]]) S.pi[(size_t)kept++] = S.pi[(size_t)l];
+        S.pi.resize((size_t)kept);
+        S.steps = kept;
     }
 }
 
@@ -248,7 +267,7 @@ int cc_step_begin(Context& c, Workspace& w, std::vector<ActiveSample>& act, CCPe
     for (size_t ai = 0; ai < act.size(); ++ai) {
         CCJob& J = *act[ai].job;
         CCSample& S = J.samples[(size_t)act[ai].s];
-        if (J.n == 0 || S.k > J.n) continue;
+        if (J.n == 0 || S.k > S.steps) continue;
         const int k = S.k;
         CCStep st;
         std::memset(&st, 0, sizeof st);
@@ -353,7 +372,7 @@ int cc_step_end(Workspace& w, std::vector<ActiveSample>& act, CCPending& p, doub
         S.prefix.push_back(drawn[i]);
         S.tv += tv[i];
         S.k++;
-        if (S.k > a.job->n) finish_sample(*a.job, a.s);
+        if (S.k > S.steps) finish_sample(*a.job, a.s);
     }
     return BBFG_OK;
 }
@@ -387,11 +406,15 @@ int run_job(Context& c, CCJob& job, int32_t* out_occupation, bbfg_info* info)
     for (int s0 = 0; s0 < job.n_samples; s0 += kWaveSamples) {
         const int s1 = std::min(job.n_samples, s0 + kWaveSamples);
         std::vector<ActiveSample> act;
+        int max_steps = 0;
         for (int s = s0; s < s1; ++s) {
             cc_start_sample(job, s);
-            act.push_back({&job, s});
+            const int st = job.samples[(size_t)s].steps;
+            if (st == 0) finish_sample(job, s);  // every photon lost
+            else act.push_back({&job, s});
+            max_steps = std::max(max_steps, st);
         }
-        for (int k = 1; k <= job.n; ++k) BBFG_TRY(cc_step(c, act, &kms, &adds, nullptr, nullptr, &fl));
+        for (int k = 1; k <= max_steps; ++k) BBFG_TRY(cc_step(c, act, &kms, &adds, nullptr, nullptr, &fl));
     }
     std::memcpy(out_occupation, job.out.data(), sizeof(int32_t) * job.out.size());
     if (info) {
@@ -424,6 +447,31 @@ try {
     CCJob job;
     BBFG_TRY(cc_job_init(*c, job, reinterpret_cast<const double*>(U), is_device_ptr(U), m, input_occupation, n_samples,
                          loss, seed));
+    return run_job(*c, job, out_occupation, info);
+}
+BBFG_API_CATCH
+
+extern "C" int bs_sample_extracted(const bbfg_c128* U, int32_t m, const int32_t* input_occupation, int32_t n_samples,
+                                   double loss, uint64_t seed, int32_t* out_occupation, bbfg_info* info)
+try {
+    BBFG_TRY(cc_validate(U, m, input_occupation, n_samples, loss));
+    if (n_samples > 0 && !out_occupation) return set_error(BBFG_EINVAL, "out_occupation is NULL");
+    if (info) std::memset(info, 0, sizeof *info);
+    if (n_samples == 0) return BBFG_OK;
+    int64_t n = 0;
+    for (int i = 0; i < m; ++i) n += input_occupation[i];
+    if (n == 0) {
+        std::memset(out_occupation, 0, sizeof(int32_t) * (size_t)n_samples * (size_t)m);
+        return BBFG_OK;
+    }
+    Context* c = nullptr;
+    BBFG_TRY(get_context(&c));
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    CCJob job;
+    // the job matrix of the ideal experiment (U's m rows); the loss acts on the inputs
+    BBFG_TRY(cc_job_init(*c, job, reinterpret_cast<const double*>(U), is_device_ptr(U), m, input_occupation, n_samples,
+                         0.0, seed));
+    job.keep = 1.0 - loss;
     return run_job(*c, job, out_occupation, info);
 }
 BBFG_API_CATCH

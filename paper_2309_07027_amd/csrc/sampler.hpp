@@ -16,7 +16,8 @@ uint64_t splitmix64_draw(uint64_t key, uint64_t c);
 
 struct CCSample {
     uint64_t key = 0;
-    int k = 1;                    // next step (1-based); > n when finished
+    int k = 1;                    // next step (1-based); > steps when finished
+    int steps = 0;                // photons sampled (n, or the survivors of an input loss)
     std::vector<int32_t> pi;      // column order
     std::vector<int32_t> prefix;  // drawn output rows r_1 .. r_{k-1}
     double tv = 0.0;              // sum over its steps of the draw-distribution error estimates
@@ -28,6 +29,7 @@ struct CCJob {
     int n = 0;          // photons
     int n_samples = 0;
     double loss = 0.0;
+    double keep = 1.0;  // < 1: uniform loss taken out at the input, each photon kept with this probability
     uint64_t seed = 0;
     std::vector<int32_t> cols;  // input mode of each column (expanded occupation)
     DevBuf A;                   // rows x n complex, device

@@ -273,7 +273,7 @@ void bbfg_server::run()
                 for (auto& j : active)
                     if (j->half == which)
                         for (int s = 0; s < j->n_samples; ++s)
-                            if (j->cc->n > 0 && j->cc->samples[(size_t)s].k <= j->cc->n)
+                            if (j->cc->n > 0 && j->cc->samples[(size_t)s].k <= j->cc->samples[(size_t)s].steps)
                                 h.act.push_back({j->cc.get(), s});
                 if (!h.act.empty()) rc = cc_step_begin(*ctx, h.ws, h.act, h.pend, nullptr);
             }

@@ -272,6 +272,37 @@ def test_bs_sample_lossy_matches_oracle_sampler(oracle, m, occ, seed):
         assert 0.0 <= info["rel_err_est"] < 1e-9
 
 
+@pytest.mark.parametrize("m,n,loss,seed", [(12, 6, 0.3, 5), (12, 8, 0.6, 6), (60, 16, 0.5, 7), (60, 20, 0.4, 8)])
+def test_bs_sample_extracted_matches_oracle_sampler(oracle, m, n, loss, seed):
+    """Uniform loss taken out at the input (Sec. 4): each photon survives with
+    probability 1 - loss and the survivors are sampled on U's m modes.  The
+    same draws give the same samples as the oracle's extraction sampler."""
+    U = I.haar_unitary(60 + seed, m)
+    occ = np.zeros(m, dtype=np.int32)
+    occ[:n] = 1
+    say(f"case bs_sample_extracted m={m} n={n} loss={loss}")
+    g, info = B.bs_sample_extracted(U, occ, 30, loss, seed, with_info=True)
+    c = oracle.cc_sample_extracted(U, occ, 30, loss, seed)
+    compare_samples(g, c, f"extracted m={m} n={n} loss={loss}")
+    assert (g.sum(axis=1) <= n).all()
+    assert 0.0 <= info["rel_err_est"] < 1e-6
+
+
+def test_bs_sample_extracted_edges():
+    """No loss: exactly the ideal samples of bs_sample.  Heavy loss: samples
+    with no surviving photon are all-zero rows, and the number of survivors
+    follows Binomial(n, 1 - loss)."""
+    U = I.haar_unitary(70, 10)
+    occ = [1, 1, 0, 2, 1, 0, 0, 1, 0, 0]
+    assert np.array_equal(B.bs_sample_extracted(U, occ, 40, 0.0, 3), B.bs_sample(U, occ, 40, 0.0, 3))
+    N, n, keep = 3000, 6, 0.15
+    s = B.bs_sample_extracted(U, occ, N, 1 - keep, 4)
+    k = s.sum(axis=1)
+    assert (k == 0).any() and (k <= n).all()
+    assert abs(k.mean() - n * keep) < 4 * np.sqrt(n * keep * (1 - keep) / N)
+    assert abs((k == 0).mean() - (1 - keep) ** n) < 4 * np.sqrt((1 - keep) ** n / N)
+
+
 def test_lossy_per_mode_photon_survival():
     """Losses at the inputs, T = U diag(sqrt(eta)): each photon entering mode i
     is detected with probability eta_i, independently, so the number detected
