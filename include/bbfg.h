@@ -397,6 +397,12 @@ int bs_server_submit(bbfg_server *srv, const bbfg_c128 *U, int32_t m, const int3
 int bs_server_submit_lossy(bbfg_server *srv, const bbfg_c128 *T, int32_t m, const int32_t *input_occupation,
                            int32_t n_samples, uint64_t seed, uint64_t *job_id);
 
+/* Queue a job whose uniform loss is applied to the input photons (arguments
+ * and samples as bs_sample_extracted; U is copied before the call returns).
+ * Errors: BBFG_EINVAL, BBFG_ERANGE. */
+int bs_server_submit_extracted(bbfg_server *srv, const bbfg_c128 *U, int32_t m, const int32_t *input_occupation,
+                               int32_t n_samples, double loss, uint64_t seed, uint64_t *job_id);
+
 /* Non-blocking: BBFG_EBUSY while the job runs; on completion copies
  * n_samples x m occupations to out_occupation (host), the job's latency
  * (completion - submission, seconds) to latency_s (nullable) and its error

@@ -100,6 +100,8 @@ SIGNATURES = {
                                         ctypes.POINTER(ctypes.c_uint64)]),
     "bs_server_submit_lossy": (ctypes.c_int, [_P, _P, _I32, _PI32, _I32, ctypes.c_uint64,
                                               ctypes.POINTER(ctypes.c_uint64)]),
+    "bs_server_submit_extracted": (ctypes.c_int, [_P, _P, _I32, _PI32, _I32, ctypes.c_double, ctypes.c_uint64,
+                                                  ctypes.POINTER(ctypes.c_uint64)]),
     "bs_server_poll": (ctypes.c_int, [_P, ctypes.c_uint64, _PI32, _PD, _PD]),
     "bs_server_cancel": (ctypes.c_int, [_P, ctypes.c_uint64]),
     "bs_server_drain": (ctypes.c_int, [_P]),
@@ -376,6 +378,16 @@ class Server:
         jid = ctypes.c_uint64()
         _check(lib().bs_server_submit_lossy(self._h, ptr, shape[0], po, int(n_samples),
                                             ctypes.c_uint64(seed & (2**64 - 1)), ctypes.byref(jid)))
+        self._m[jid.value] = (int(n_samples), shape[0])
+        del keep
+        return jid.value
+
+    def submit_extracted(self, U, input_occupation, n_samples: int, loss: float = 0.0, seed: int = 0) -> int:
+        ptr, keep, shape = _cmat_ptr(U)
+        occ, po = _i32(input_occupation)
+        jid = ctypes.c_uint64()
+        _check(lib().bs_server_submit_extracted(self._h, ptr, shape[0], po, int(n_samples), float(loss),
+                                                ctypes.c_uint64(seed & (2**64 - 1)), ctypes.byref(jid)))
         self._m[jid.value] = (int(n_samples), shape[0])
         del keep
         return jid.value

@@ -183,6 +183,21 @@ int cc_job_init_matrix(Context& c, CCJob& job, const double* A_host, int rows, i
     return BBFG_OK;
 }
 
+namespace {
+
+void finish_sample(CCJob& job, int s)
+{
+    const CCSample& S = job.samples[(size_t)s];
+    int32_t* o = job.out.data() + (size_t)s * (size_t)job.m;
+    for (int i = 0; i < job.m; ++i) o[i] = 0;
+    for (int32_t r : S.prefix)
+        if (r < job.m) o[r]++;
+    job.tv_max = std::max(job.tv_max, S.tv);
+    job.finished++;
+}
+
+}  // namespace
+
 void cc_start_sample(CCJob& job, int s)
 {
     CCSample& S = job.samples[(size_t)s];
@@ -210,22 +225,9 @@ void cc_start_sample(CCJob& job, int s)
         S.pi.resize((size_t)kept);
         S.steps = kept;
     }
+    if (S.steps == 0) finish_sample(job, s);  // every photon lost: an empty sample
 }
 
-namespace {
-
-void finish_sample(CCJob& job, int s)
-{
-    const CCSample& S = job.samples[(size_t)s];
-    int32_t* o = job.out.data() + (size_t)s * (size_t)job.m;
-    for (int i = 0; i < job.m; ++i) o[i] = 0;
-    for (int32_t r : S.prefix)
-        if (r < job.m) o[r]++;
-    job.tv_max = std::max(job.tv_max, S.tv);
-    job.finished++;
-}
-
-}  // namespace
 
 void add_minor_items(const PermItem& proto, const int32_t* cols, std::deque<std::vector<int32_t>>& keep,
                      std::vector<PermItem>& items, uint64_t res_first, uint32_t* slot)
@@ -410,8 +412,7 @@ int run_job(Context& c, CCJob& job, int32_t* out_occupation, bbfg_info* info)
         for (int s = s0; s < s1; ++s) {
             cc_start_sample(job, s);
             const int st = job.samples[(size_t)s].steps;
-            if (st == 0) finish_sample(job, s);  // every photon lost
-            else act.push_back({&job, s});
+            if (st > 0) act.push_back({&job, s});  // an empty sample is finished at its start
             max_steps = std::max(max_steps, st);
         }
         for (int k = 1; k <= max_steps; ++k) BBFG_TRY(cc_step(c, act, &kms, &adds, nullptr, nullptr, &fl));

@@ -91,7 +91,9 @@ int cc_lossy_job_matrix(const double* T, int m, const int32_t* occ, std::vector<
 int cc_job_init_matrix(Context& c, CCJob& job, const double* A_host, int rows, int m, const int32_t* occ,
                        int n_samples, uint64_t seed, bool stage_pinned = false);
 
-// Draws sample s's column order (Fisher-Yates with SplitMix64).
+// Draws sample s's column order (Fisher-Yates with SplitMix64) and, when the
+// job keeps photons with probability keep < 1, its surviving photons; a sample
+// left without photons is finished at once (an all-zero occupation).
 void cc_start_sample(CCJob& job, int s);
 
 // One step of every listed sample, in two halves so that a caller can prepare

@@ -41,6 +41,7 @@ struct SJob {
     std::vector<int32_t> occ;
     int n_samples = 0;
     double loss = 0.0;
+    double keep = 1.0;      // input-loss jobs: each photon kept with this probability
     uint64_t seed = 0;
     size_t footprint = 0;
     Clock::time_point t_submit, t_done;
@@ -260,6 +261,7 @@ void bbfg_server::run()
                     rc = cc_job_init(*ctx, *j->cc, j->U.data(), false, j->m, j->occ.data(), j->n_samples, j->loss,
                                      j->seed, true);
                 if (rc != BBFG_OK) break;
+                j->cc->keep = j->keep;
                 for (int s = 0; s < j->n_samples; ++s) cc_start_sample(*j->cc, s);
                 // work ~ samples x the addends of the last (largest) steps
                 j->weight = (double)j->n_samples * std::ldexp(1.0, std::min(j->cc->n, 60));
@@ -301,11 +303,17 @@ void bbfg_server::run()
 
 namespace {
 
-// Queues a job; with `lossy_matrix`, U is the m x m lossy interferometer
-// matrix T and the job matrix [T; R] is built (and T validated) here.
+// How a job's loss is simulated.
+enum class LossMode { kDilation, kMatrix, kInput };
+
+// Queues a job.  kDilation: the scalar loss by the 2m x 2m dilation;
+// kMatrix: U is the m x m lossy interferometer matrix T and the job matrix
+// [T; R] is built (and T validated) here; kInput: the scalar loss applied to
+// the input photons, survivors sampled with U (bs_sample_extracted).
 int submit_job(bbfg_server* srv, const bbfg_c128* U, int32_t m, const int32_t* input_occupation, int32_t n_samples,
-               double loss, uint64_t seed, bool lossy_matrix, uint64_t* job_id)
+               double loss, uint64_t seed, LossMode mode, uint64_t* job_id)
 {
+    const bool lossy_matrix = mode == LossMode::kMatrix;
     if (!srv || !job_id) return set_error(BBFG_EINVAL, "NULL argument");
     BBFG_TRY(cc_validate(U, m, input_occupation, n_samples, lossy_matrix ? 0.5 : loss));
     auto j = std::make_shared<SJob>();
@@ -324,9 +332,10 @@ int submit_job(bbfg_server* srv, const bbfg_c128* U, int32_t m, const int32_t* i
     int n = 0;
     for (int i = 0; i < m; ++i) n += input_occupation[i];
     j->n_samples = n_samples;
-    j->loss = lossy_matrix ? 0.0 : loss;
+    j->loss = mode == LossMode::kDilation ? loss : 0.0;
+    j->keep = mode == LossMode::kInput ? 1.0 - loss : 1.0;
     j->seed = seed;
-    j->footprint = cc_job_footprint(m, n, n_samples, lossy_matrix ? 0.5 : loss);
+    j->footprint = cc_job_footprint(m, n, n_samples, lossy_matrix ? 0.5 : j->loss);
     j->t_submit = Clock::now();
     std::lock_guard<std::mutex> lk(srv->mu);
     if (srv->init_error != BBFG_OK) return set_error(srv->init_error, "%s", srv->init_message.c_str());
@@ -372,14 +381,21 @@ BBFG_API_CATCH
 int bs_server_submit(bbfg_server* srv, const bbfg_c128* U, int32_t m, const int32_t* input_occupation,
                      int32_t n_samples, double loss, uint64_t seed, uint64_t* job_id)
 try {
-    return submit_job(srv, U, m, input_occupation, n_samples, loss, seed, false, job_id);
+    return submit_job(srv, U, m, input_occupation, n_samples, loss, seed, LossMode::kDilation, job_id);
+}
+BBFG_API_CATCH
+
+int bs_server_submit_extracted(bbfg_server* srv, const bbfg_c128* U, int32_t m, const int32_t* input_occupation,
+                               int32_t n_samples, double loss, uint64_t seed, uint64_t* job_id)
+try {
+    return submit_job(srv, U, m, input_occupation, n_samples, loss, seed, LossMode::kInput, job_id);
 }
 BBFG_API_CATCH
 
 int bs_server_submit_lossy(bbfg_server* srv, const bbfg_c128* T, int32_t m, const int32_t* input_occupation,
                            int32_t n_samples, uint64_t seed, uint64_t* job_id)
 try {
-    return submit_job(srv, T, m, input_occupation, n_samples, 0.0, seed, true, job_id);
+    return submit_job(srv, T, m, input_occupation, n_samples, 0.0, seed, LossMode::kMatrix, job_id);
 }
 BBFG_API_CATCH
 

@@ -380,6 +380,26 @@ def test_server_lossy_jobs_and_cancel():
         assert np.array_equal(srv.poll(j2)[0], alone)
 
 
+def test_server_extracted_jobs_equal_alone():
+    """Input-loss jobs through the server (mixed with ideal jobs, one of them at
+    a loss that leaves many samples without photons) equal bs_sample_extracted
+    alone, sample for sample."""
+    U = I.haar_unitary(81, 60)
+    occ = np.zeros(60, dtype=np.int32)
+    occ[:20] = 1
+    cases = [(0.5, 11), (0.95, 12), (0.2, 13)]
+    alone = [B.bs_sample_extracted(U, occ, 16, loss, seed) for loss, seed in cases]
+    ideal = B.bs_sample(U, occ, 8, 0.0, 14)
+    with B.Server(max_active_jobs=4) as srv:
+        jid = [srv.submit_extracted(U, occ, 16, loss, seed) for loss, seed in cases]
+        j_ideal = srv.submit(U, occ, 8, seed=14)
+        srv.drain()
+        for j, a in zip(jid, alone):
+            assert np.array_equal(srv.poll(j)[0], a)
+        assert np.array_equal(srv.poll(j_ideal)[0], ideal)
+    assert (alone[1].sum(axis=1) == 0).any()
+
+
 def test_sampler_error_estimate_reported():
     """Every sample's law carries an error estimate (sum over its steps of the
     draw distribution's estimated total-variation error, from the minors'
