@@ -963,9 +963,38 @@ int oracle_contraction_isometry(int m, const double *T, double *V)
     return contraction_isometry(m, T, V);
 }
 
+/* The uniform part of the loss of T (Sec. 4): the transmission eta_u such
+ * that T = sqrt(eta_u) T' leaves T' a contraction, taken as the Gershgorin
+ * bound max_j sum_k |(T^H T)_jk| of the largest eigenvalue of T^H T (exact
+ * for T^H T diagonal, as for losses at the inputs or a uniform loss; an upper
+ * bound otherwise, so T' is a contraction whenever T is); 1 when the bound
+ * reaches 1 (nothing is taken out). */
+static double uniform_transmission(int m, const double *T)
+{
+    double bound = 0.0;
+    for (int j = 0; j < m; ++j) {
+        double row = 0.0;
+        for (int k = 0; k < m; ++k) {
+            double re = 0.0, im = 0.0;
+            for (int i = 0; i < m; ++i) {
+                const double *a = T + 2 * (i * m + j), *b = T + 2 * (i * m + k);
+                re += a[0] * b[0] + a[1] * b[1]; /* conj(a) b */
+                im += a[0] * b[1] - a[1] * b[0];
+            }
+            row += sqrt(re * re + im * im);
+        }
+        if (row > bound) bound = row;
+    }
+    return bound < 1.0 ? bound : 1.0;
+}
+
 /* Clifford & Clifford samples through the lossy interferometer T (m x m
- * contraction): the 2m rows of V = [T; R] are the candidate output modes, the
- * first m are reported.  Random numbers as in oracle_cc_sample. */
+ * contraction).  Its uniform part eta_u (uniform_transmission) is taken out
+ * at the input (Sec. 4): each photon survives with probability eta_u, as in
+ * oracle_cc_sample_extracted, and the survivors are sampled through
+ * T' = T / sqrt(eta_u): the 2m rows of V = [T'; R'] are the candidate output
+ * modes, the first m are reported.  Random numbers as in oracle_cc_sample,
+ * plus the survival draws of oracle_cc_sample_extracted when eta_u < 1. */
 int oracle_cc_sample_lossy(int m, const double *T, const int *input_occ, int n_samples, uint64_t seed,
                            int *out_occ)
 {
@@ -973,9 +1002,21 @@ int oracle_cc_sample_lossy(int m, const double *T, const int *input_occ, int n_s
     int n = count_photons(m, input_occ);
     if (n < 0 || n > 24) return -1;
     double *V = (double *)malloc(sizeof(double) * 2 * (size_t)(2 * m) * (size_t)m);
-    if (!V) return -2;
-    int rc = contraction_isometry(m, T, V);
-    if (rc == 0) rc = cc_sample_rows(2 * m, m, V, m, input_occ, n, n_samples, seed, out_occ);
+    double *Ts = (double *)malloc(sizeof(double) * 2 * (size_t)m * (size_t)m);
+    if (!V || !Ts) { free(V); free(Ts); return -2; }
+    const double keep = uniform_transmission(m, T);
+    const double scale = keep > 0.0 ? 1.0 / sqrt(keep) : 1.0;
+    for (size_t i = 0; i < 2 * (size_t)m * (size_t)m; ++i) Ts[i] = T[i] * scale;
+    int rc = contraction_isometry(m, Ts, V);
+    if (rc == 0) rc = cc_sample_rows_kept(2 * m, m, V, m, input_occ, n, n_samples, seed, keep, out_occ);
     free(V);
+    free(Ts);
     return rc;
+}
+
+/* eta_u of T, for the tests. */
+double oracle_uniform_transmission(int m, const double *T)
+{
+    if (m < 1 || m > 128) return -1.0;
+    return uniform_transmission(m, T);
 }

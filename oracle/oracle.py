@@ -73,6 +73,8 @@ def lib():
         L.oracle_cc_sample_lossy.argtypes = [ctypes.c_int, _D, _I, ctypes.c_int, ctypes.c_uint64, _I]
         L.oracle_cc_sample_extracted.argtypes = [ctypes.c_int, _D, _I, ctypes.c_int, ctypes.c_double,
                                                  ctypes.c_uint64, _I]
+        L.oracle_uniform_transmission.argtypes = [ctypes.c_int, _D]
+        L.oracle_uniform_transmission.restype = ctypes.c_double
         _lib = L
     return _lib
 
@@ -286,6 +288,12 @@ def cc_sample_extracted(U, input_occ, n_samples: int, loss: float, seed: int) ->
     if rc:
         raise ValueError(f"oracle_cc_sample_extracted rc={rc}")
     return out
+
+
+def uniform_transmission(T) -> float:
+    """The uniform part of T's loss taken out at the input by cc_sample_lossy."""
+    T = _cmat(T)
+    return float(lib().oracle_uniform_transmission(T.shape[0], _dp(T)))
 
 
 def contraction_isometry(T) -> np.ndarray:

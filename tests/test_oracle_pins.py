@@ -637,6 +637,46 @@ def test_lossy_matrix_marginal_matches_per_mode_loss(oracle, where):
     assert abs(total - 1.0) < 1e-13
 
 
+def test_uniform_transmission_of_lossy_matrices(oracle):
+    # the uniform part taken out of T: exact for a uniform loss and for losses
+    # at the inputs (T^H T diagonal), an upper bound of the largest eigenvalue
+    # of T^H T otherwise, never above 1
+    from paper_2309_07027_amd.inputs import haar_unitary
+    m = 6
+    U = haar_unitary(48, m)
+    eta = np.array([0.5, 0.3, 0.6, 0.45, 0.2, 0.55])
+    assert abs(oracle.uniform_transmission(np.sqrt(0.37) * U) - 0.37) < 1e-14
+    assert abs(oracle.uniform_transmission(U * np.sqrt(eta)[None, :]) - eta.max()) < 1e-14
+    T = np.sqrt(eta)[:, None] * U
+    lam = np.linalg.eigvalsh(T.conj().T @ T).max()
+    u = oracle.uniform_transmission(T)
+    assert lam - 1e-14 <= u <= 1.0
+    assert oracle.uniform_transmission(U) == 1.0
+
+
+def test_lossy_matrix_sampler_law_with_uniform_part(oracle):
+    # every input mode lossy: the uniform part (the largest transmission) is
+    # taken out at the input and the rest stays in T; the law is unchanged
+    from paper_2309_07027_amd.inputs import haar_unitary
+    m = 4
+    U = haar_unitary(49, m)
+    eta = np.array([0.5, 0.3, 0.6, 0.45])
+    T = U * np.sqrt(eta)[None, :]
+    V = oracle.contraction_isometry(T)
+    occ = [1, 1, 1, 0]
+    N = 20000
+    samples = oracle.cc_sample_lossy(T, occ, N, 323)
+    counts = {}
+    for s in samples:
+        counts[tuple(s)] = counts.get(tuple(s), 0) + 1
+    tv = 0.0
+    for kept in range(4):
+        for Tp in patterns(m, kept):
+            tv += abs(counts.get(Tp, 0) / N - _lossy_marginal(oracle, V, m, occ, Tp))
+    assert 0.5 * tv < 0.03
+    assert abs(samples.sum(axis=1).mean() - eta[:3].sum()) < 4 * math.sqrt(3 * 0.25 / N)
+
+
 def test_lossy_matrix_sampler_law(oracle):
     from paper_2309_07027_amd.inputs import haar_unitary
     m = 4
