@@ -334,12 +334,16 @@ int bs_sample(const bbfg_c128 *U, int32_t m, const int32_t *input_occupation, in
  *                     as bs_sample (1 <= m <= 128); info->rel_err_est as
  *                     bs_sample.
  *
- * The photons enter the first m of 2m modes of the isometry [T; R] (R the
- * upper-triangular Cholesky factor of I - T^H T, built on the host); all 2m
+ * The uniform part of the loss, eta_u = min(1, max_j sum_k |(T^H T)_jk|) (a
+ * bound of T^H T's largest eigenvalue, exact for uniform and input losses), is
+ * taken out at the input as in bs_sample_extracted (each photon survives with
+ * probability eta_u, same random numbers); the survivors enter the first m of
+ * 2m modes of the isometry [T'; R], T' = T / sqrt(eta_u) (R the
+ * upper-triangular Cholesky factor of I - T'^H T', built on the host); all 2m
  * rows are candidate outputs and the first m are reported.  Every R with
- * R^H R = I - T^H T gives the same law on the first m modes, so for T =
+ * R^H R = I - T'^H T' gives the same law on the first m modes, so for T =
  * sqrt(eta) U the law is that of bs_sample with loss 1 - eta, though not the
- * same samples (bs_sample uses the block dilation).
+ * same samples.
  * Errors: as bs_sample; BBFG_EINVAL also when T is not a contraction (a pivot
  * of I - T^H T below -1e-10).
  */

@@ -110,18 +110,33 @@ int cc_job_init(Context& c, CCJob& job, const double* U, bool U_on_device, int m
     return BBFG_OK;
 }
 
-int cc_lossy_job_matrix(const double* T, int m, const int32_t* occ, std::vector<double>& A)
+int cc_lossy_job_matrix(const double* T, int m, const int32_t* occ, std::vector<double>& A, double* keep)
 {
     using cd = std::complex<double>;
     const cd* t = reinterpret_cast<const cd*>(T);
-    // G = I - T^H T (Hermitian); overwritten by the trailing updates below
-    std::vector<cd> G((size_t)m * (size_t)m), R((size_t)m * (size_t)m, cd(0.0, 0.0));
+    // H = T^H T (Hermitian), all of it for the row sums of the bound
+    std::vector<cd> H((size_t)m * (size_t)m);
     for (int j = 0; j < m; ++j)
-        for (int k = j; k < m; ++k) {
+        for (int k = 0; k < m; ++k) {
             cd acc(0.0, 0.0);
             for (int i = 0; i < m; ++i) acc += std::conj(t[(size_t)i * m + j]) * t[(size_t)i * m + k];
-            G[(size_t)j * m + k] = (j == k ? cd(1.0, 0.0) : cd(0.0, 0.0)) - acc;
+            H[(size_t)j * m + k] = acc;
         }
+    double bound = 0.0;
+    for (int j = 0; j < m; ++j) {
+        double row = 0.0;
+        for (int k = 0; k < m; ++k) row += std::abs(H[(size_t)j * m + k]);
+        bound = std::max(bound, row);
+    }
+    *keep = std::min(bound, 1.0);
+    // the rest T' = T / sqrt(keep): its Gram matrix is H / keep
+    const double inv = *keep > 0.0 ? 1.0 / *keep : 1.0;
+    const double scale = *keep > 0.0 ? 1.0 / std::sqrt(*keep) : 1.0;
+    // G = I - T'^H T' (upper triangle); overwritten by the trailing updates below
+    std::vector<cd> G((size_t)m * (size_t)m), R((size_t)m * (size_t)m, cd(0.0, 0.0));
+    for (int j = 0; j < m; ++j)
+        for (int k = j; k < m; ++k)
+            G[(size_t)j * m + k] = (j == k ? cd(1.0, 0.0) : cd(0.0, 0.0)) - H[(size_t)j * m + k] * inv;
     // right-looking Cholesky of the upper triangle: row j of R from the pivot,
     // then the trailing block loses the outer product of that row
     constexpr double kTol = 1e-10;
@@ -142,7 +157,7 @@ int cc_lossy_job_matrix(const double* T, int m, const int32_t* occ, std::vector<
     A.assign(2 * (size_t)(2 * m) * n, 0.0);
     for (int r = 0; r < 2 * m; ++r)
         for (size_t b = 0; b < n; ++b) {
-            const cd x = r < m ? t[(size_t)r * m + cols[b]] : R[(size_t)(r - m) * m + cols[b]];
+            const cd x = r < m ? t[(size_t)r * m + cols[b]] * scale : R[(size_t)(r - m) * m + cols[b]];
             A[2 * ((size_t)r * n + b)] = x.real();
             A[2 * ((size_t)r * n + b) + 1] = x.imag();
         }
@@ -490,7 +505,8 @@ try {
         std::memcpy(Th.data(), T, sizeof(double) * Th.size());
     }
     std::vector<double> A;
-    BBFG_TRY(cc_lossy_job_matrix(Th.data(), m, input_occupation, A));
+    double keep = 1.0;
+    BBFG_TRY(cc_lossy_job_matrix(Th.data(), m, input_occupation, A, &keep));
     if (info) std::memset(info, 0, sizeof *info);
     if (n_samples == 0) return BBFG_OK;
     int64_t n = 0;
@@ -504,6 +520,7 @@ try {
     std::lock_guard<std::recursive_mutex> lk(c->mu);
     CCJob job;
     BBFG_TRY(cc_job_init_matrix(*c, job, A.data(), 2 * m, m, input_occupation, n_samples, seed));
+    job.keep = keep;
     return run_job(*c, job, out_occupation, info);
 }
 BBFG_API_CATCH

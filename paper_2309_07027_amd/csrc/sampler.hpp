@@ -77,13 +77,17 @@ size_t cc_job_footprint(int m, int n, int n_samples, double loss);
 int cc_job_init(Context& c, CCJob& job, const double* U, bool U_on_device, int m, const int32_t* occ, int n_samples,
                 double loss, uint64_t seed, bool stage_pinned = false);
 
-// Non-uniform loss (Sec. 4): the 2m x n job matrix of photons entering the
-// input modes of the m x m lossy interferometer matrix T (host, row-major
-// complex): the input columns of the isometry [T; R], R the upper-triangular
-// Cholesky factor of I - T^H T.  Any B with B^H B = I - T^H T gives the same
-// law on the first m output modes; R is one.  Fails with BBFG_EINVAL when T
-// is not a contraction (a pivot of I - T^H T below -1e-10).
-int cc_lossy_job_matrix(const double* T, int m, const int32_t* occ, std::vector<double>& A);
+// Non-uniform loss (Sec. 4): the uniform part of T's loss, *keep (the
+// Gershgorin bound max_j sum_k |(T^H T)_jk| of T^H T's largest eigenvalue,
+// capped at 1: exact for uniform and input losses), is taken out at the input
+// (each photon survives with that probability), and the 2m x n job matrix of
+// photons entering the input modes of the rest, T' = T / sqrt(*keep) (host,
+// row-major complex), is built: the input columns of the isometry [T'; R], R
+// the upper-triangular Cholesky factor of I - T'^H T'.  Any B with B^H B =
+// I - T'^H T' gives the same law on the first m output modes; R is one.
+// Fails with BBFG_EINVAL when T is not a contraction (a pivot of I - T^H T
+// below -1e-10).
+int cc_lossy_job_matrix(const double* T, int m, const int32_t* occ, std::vector<double>& A, double* keep);
 
 // As cc_job_init, with the job matrix built on the host (rows x n complex,
 // e.g. by cc_lossy_job_matrix): rows candidate output modes, the first m

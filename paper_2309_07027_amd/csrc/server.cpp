@@ -41,7 +41,7 @@ struct SJob {
     std::vector<int32_t> occ;
     int n_samples = 0;
     double loss = 0.0;
-    double keep = 1.0;      // input-loss jobs: each photon kept with this probability
+    double keep = 1.0;      // input-loss and lossy-matrix jobs: each photon kept with this probability
     uint64_t seed = 0;
     size_t footprint = 0;
     Clock::time_point t_submit, t_done;
@@ -325,7 +325,7 @@ int submit_job(bbfg_server* srv, const bbfg_c128* U, int32_t m, const int32_t* i
         std::memcpy(j->U.data(), U, sizeof(double) * j->U.size());
     }
     if (lossy_matrix) {
-        BBFG_TRY(cc_lossy_job_matrix(j->U.data(), m, input_occupation, j->A));
+        BBFG_TRY(cc_lossy_job_matrix(j->U.data(), m, input_occupation, j->A, &j->keep));
         j->U.clear();
     }
     j->occ.assign(input_occupation, input_occupation + m);
@@ -333,7 +333,7 @@ int submit_job(bbfg_server* srv, const bbfg_c128* U, int32_t m, const int32_t* i
     for (int i = 0; i < m; ++i) n += input_occupation[i];
     j->n_samples = n_samples;
     j->loss = mode == LossMode::kDilation ? loss : 0.0;
-    j->keep = mode == LossMode::kInput ? 1.0 - loss : 1.0;
+    if (mode == LossMode::kInput) j->keep = 1.0 - loss;  // kMatrix: set with the job matrix above
     j->seed = seed;
     j->footprint = cc_job_footprint(m, n, n_samples, lossy_matrix ? 0.5 : j->loss);
     j->t_submit = Clock::now();
