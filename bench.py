@@ -318,6 +318,16 @@ def large_sampling_section(B, I, samples_ideal: int, samples_lossy: int):
                                   "walk_ms": round(info["kernel_ms"], 1),
                                   "err_est_max_per_sample": float(f"{info['rel_err_est']:.3g}"),
                                   "photons_out_mean": round(float(s.sum(axis=1).mean()), 2)}
+    # the same experiment as a lossy matrix T = sqrt(0.5) U: its uniform part is taken out too
+    T = U * math.sqrt(1.0 - loss)
+    B.bs_sample_lossy(T, occ, 1, seed=1)
+    t = time.perf_counter()
+    s, info = B.bs_sample_lossy(T, occ, samples_ideal, seed=5, with_info=True)
+    dt = time.perf_counter() - t
+    out["lossy_0.5_matrix"] = {"samples": samples_ideal, "s_per_sample": round(dt / samples_ideal, 5),
+                               "walk_ms": round(info["kernel_ms"], 1),
+                               "err_est_max_per_sample": float(f"{info['rel_err_est']:.3g}"),
+                               "photons_out_mean": round(float(s.sum(axis=1).mean()), 2)}
     return out
 
 
