@@ -400,7 +400,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--large-samples", type=int, default=10,
                     help="samples of the lossy n = 40 run (0 = skip the section)")
-    ap.add_argument("--large-ideal-samples", type=int, default=40, help="samples of the ideal n = 40 run")
+    ap.add_argument("--large-ideal-samples", type=int, default=100,
+                    help="samples of the ideal n = 40 run (the paper averages 100)")
     ap.add_argument("--no-t0-fit", action="store_true", help="skip the sampling-time model fit")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run one plain device-to-device copy of this size (HBM counter calibration)")
