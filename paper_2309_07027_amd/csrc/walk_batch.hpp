@@ -34,13 +34,16 @@ __device__ __forceinline__ void dispatch_unit(const WalkArgs& A, const PermDesc&
 // unit from the counter and hands it to the wavefront through LDS between two
 // barriers, so every lane leaves the loop at the same iteration.
 // POW: items carry column multiplicities (their own kernels, walk_cols_b*.hip).
-// The FP64 kernel for up to 24 columns is built for four wavefronts per SIMD
-// (128 VGPRs; it would take 143 and three): the few values that no longer fit
-// are spilled outside the walk loop, and the 4096-item batch ran 3 % faster.
+// The kernels for up to 24 columns are built for more wavefronts per SIMD than
+// their registers would give: FP64 four (128 VGPRs; it would take 143 and
+// three), FP32 six (80 VGPRs instead of 83 and five).  The few values that no
+// longer fit are spilled outside the walk loop; the 4096-item batch ran 3 %
+// (FP64) and 1 % (FP32) faster.
 template <int NMAX, typename Real, bool POW>
 constexpr int batch_waves_per_simd()
 {
-    return (NMAX == 24 && sizeof(Real) == 8 && !POW) ? 4 : 1;
+    if (NMAX != 24 || POW) return 1;
+    return sizeof(Real) == 8 ? 4 : 6;
 }
 
 template <int NMAX, typename Real, bool POW = false>
